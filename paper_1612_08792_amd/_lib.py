@@ -1,0 +1,89 @@
+"""ctypes declarations of the gmmsp C ABI (include/gmmsp.h).
+
+Argument marshalling only: every step of the method runs in libgmmsp.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmmsp.so")
+
+GMMSP_OK = 0
+GMMSP_E_INVAL = -1
+GMMSP_E_SIZE = -2
+GMMSP_E_HIP = -3
+GMMSP_E_STATE = -5
+THETA_ROW = 13
+LL_CAP = 4096
+
+
+class GmmspParams(ctypes.Structure):
+    _fields_ = [("W", c_int32), ("H", c_int32), ("K", c_int32), ("vx", c_int32),
+                ("vy", c_int32), ("eps_s", c_double), ("eps_c", c_double),
+                ("lam", c_double), ("cov_mode", c_int32), ("n_min", c_double)]
+
+
+class GmmspGridInfo(ctypes.Structure):
+    _fields_ = [("vx", c_int32), ("vy", c_int32), ("nx", c_int32), ("ny", c_int32),
+                ("K", c_int32), ("ncx", c_int32), ("ncy", c_int32)]
+
+
+class GmmspError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gmmsp error {code}: {msg}")
+        self.code = code
+
+
+_SIGS = {
+    "gmmsp_grid": (c_int, [POINTER(GmmspParams), POINTER(GmmspGridInfo)]),
+    "gmmsp_workspace_bytes": (c_int, [c_int32, POINTER(GmmspParams), POINTER(c_size_t)]),
+    "gmmsp_create": (c_int, [c_int32, POINTER(GmmspParams), c_void_p, c_size_t, c_void_p,
+                             POINTER(c_void_p)]),
+    "gmmsp_destroy": (c_int, [c_void_p]),
+    "gmmsp_batch_info": (c_int, [c_void_p, POINTER(c_int32), POINTER(c_int64), POINTER(c_int64)]),
+    "gmmsp_image_grid": (c_int, [c_void_p, c_int32, POINTER(GmmspGridInfo)]),
+    "gmmsp_init_seeds": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_set_params_dev": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_set_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_get_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_em_iterate": (c_int, [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_void_p]),
+    "gmmsp_ll_history": (c_int, [c_void_p, c_int32, c_void_p, c_int32, POINTER(c_int32),
+                                 c_void_p]),
+    "gmmsp_label": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gmmsp_export_responsibilities": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gmmsp_export_candidates": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_profile_enable": (c_int, [c_void_p, c_int32]),
+    "gmmsp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
+                                   POINTER(c_int64), c_int32]),
+    "gmmsp_last_error": (c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgmmsp.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(rc: int):
+    if rc != GMMSP_OK:
+        raise GmmspError(rc, lib().gmmsp_last_error().decode())
+    return rc

@@ -1,0 +1,460 @@
+// Host side of the gmmsp C ABI: argument validation, seed-grid arithmetic
+// (Eqs. vxy, nxyK), batch tables, workspace layout and the EM driver.
+#include "../../include/gmmsp.h"
+#include "gmmsp_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace gmmsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(GMMSP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// floor(sqrt(n)) for n >= 0, exact
+int64_t isqrt64(int64_t n) {
+  int64_t r = (int64_t)sqrt((double)n);
+  while (r > 0 && r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+
+int grid_of(const gmmsp_params* p, gmmsp_grid_info* g) {
+  if (!p || !g) return fail(GMMSP_E_INVAL, "null pointer");
+  if (p->W < 1 || p->H < 1) return fail(GMMSP_E_INVAL, "image size %d x %d", p->W, p->H);
+  int64_t vx = p->vx, vy = p->vy;
+  if (vx == 0 && vy == 0) {
+    const int64_t N = (int64_t)p->W * p->H;
+    if (p->K < 1 || p->K > N) return fail(GMMSP_E_INVAL, "K = %d outside [1, %lld]", p->K, (long long)N);
+    // Eq. vxy: floor(sqrt(W H / K)) = isqrt(floor(W H / K))
+    vx = vy = isqrt64(N / p->K);
+  }
+  if (vx < 1 || vy < 1) return fail(GMMSP_E_INVAL, "seed spacing %lld x %lld", (long long)vx, (long long)vy);
+  const int64_t nx = p->W / vx, ny = p->H / vy;  // Eq. nxyK
+  if (nx < 1 || ny < 1) return fail(GMMSP_E_SIZE, "seed spacing exceeds the image");
+  g->vx = (int32_t)vx;
+  g->vy = (int32_t)vy;
+  g->nx = (int32_t)nx;
+  g->ny = (int32_t)ny;
+  g->K = (int32_t)(nx * ny);
+  g->ncx = (int32_t)((p->W + vx - 1) / vx);
+  g->ncy = (int32_t)((p->H + vy - 1) / vy);
+  return GMMSP_OK;
+}
+
+int check_params(const gmmsp_params* p) {
+  if (!(p->eps_s > 0) || !(p->eps_c > 0) || !(p->lambda > 0) || !(p->n_min >= 0))
+    return fail(GMMSP_E_INVAL, "eps_s, eps_c, lambda must be > 0 and n_min >= 0");
+  if (p->cov_mode != 0) return fail(GMMSP_E_INVAL, "cov_mode %d is not supported", p->cov_mode);
+  return GMMSP_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t img, state, ll_hist, cell, sp, theta, rec, part, n_done, total;
+  int32_t n_cell = 0, n_sp = 0;
+  int64_t n_pix = 0;
+};
+
+int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>* descs) {
+  if (n < 1 || !params) return fail(GMMSP_E_INVAL, "need at least one image");
+  int64_t n_cell = 0, n_sp = 0, n_pix = 0;
+  if (descs) descs->resize(n);
+  for (int32_t b = 0; b < n; ++b) {
+    gmmsp_grid_info g;
+    int rc = grid_of(&params[b], &g);
+    if (rc) return fail(rc, "image %d: %s", b, g_err.c_str());
+    rc = check_params(&params[b]);
+    if (rc) return fail(rc, "image %d: %s", b, g_err.c_str());
+    if (descs) {
+      ImgDesc& d = (*descs)[b];
+      memset(&d, 0, sizeof(d));
+      d.W = params[b].W; d.H = params[b].H; d.vx = g.vx; d.vy = g.vy;
+      d.nx = g.nx; d.ny = g.ny; d.ncx = g.ncx; d.ncy = g.ncy;
+      d.pix_off = n_pix;
+      d.cell_off = (int32_t)n_cell;
+      d.sp_off = (int32_t)n_sp;
+      d.K = g.K;
+      d.ncells = g.ncx * g.ncy;
+      d.eps_s = params[b].eps_s; d.eps_c = params[b].eps_c;
+      d.lam = params[b].lambda; d.n_min = params[b].n_min;
+      // ln of the largest density the eigenvalue floors allow:
+      // -(5/2) ln 2pi - (1/2)(2 ln eps_s + 3 ln eps_c)
+      d.lncmax = -2.5 * log(2.0 * M_PI) - 0.5 * (2.0 * log(d.eps_s) + 3.0 * log(d.eps_c));
+    }
+    n_cell += (int64_t)g.ncx * g.ncy;
+    n_sp += g.K;
+    n_pix += (int64_t)params[b].W * params[b].H;
+  }
+  if (n_cell > INT32_MAX / 16 || n_sp > INT32_MAX / 16) return fail(GMMSP_E_SIZE, "batch too large");
+  size_t o = 0;
+  L->img = o;     o = align256(o + sizeof(ImgDesc) * n);
+  L->state = o;   o = align256(o + sizeof(ImgState) * n);
+  L->ll_hist = o; o = align256(o + sizeof(double) * (size_t)kLLCap * n);
+  L->cell = o;    o = align256(o + sizeof(CellDesc) * n_cell);
+  L->sp = o;      o = align256(o + sizeof(SpDesc) * n_sp);
+  L->theta = o;   o = align256(o + sizeof(double) * kThetaRow * n_sp);
+  L->rec = o;     o = align256(o + sizeof(float) * kRecFloats * kSlots * n_cell);
+  L->part = o;    o = align256(o + sizeof(double) * kPartStride * n_cell);
+  L->n_done = o;  o = align256(o + sizeof(int32_t));
+  L->total = o;
+  L->n_cell = (int32_t)n_cell;
+  L->n_sp = (int32_t)n_sp;
+  L->n_pix = n_pix;
+  return GMMSP_OK;
+}
+
+}  // namespace
+
+struct gmmsp_handle {
+  int32_t n_img = 0;
+  int64_t n_pix = 0;
+  std::vector<ImgDesc> img;
+  std::vector<int64_t> pairs;  // sum_i |K_i| per image
+  DevPtrs P{};
+  bool initialised = false;
+  // E-step kernel timing
+  bool profile = false;
+  std::vector<hipEvent_t> ev;
+  double prof_ms = 0.0;
+  int32_t prof_launches = 0;
+  int64_t prof_pix = 0, prof_pairs = 0;
+  ~gmmsp_handle() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+// sum over windows of Eq. Ik along one axis: sum_k (min(n, v(k+2)) - max(0, v(k-1)))
+int64_t window_extent_sum(int64_t n_pixels, int64_t v, int64_t n_seeds) {
+  int64_t s = 0;
+  for (int64_t k = 0; k < n_seeds; ++k) {
+    const int64_t b = v * (k - 1) > 0 ? v * (k - 1) : 0;
+    const int64_t e = v * (k + 2) < n_pixels ? v * (k + 2) : n_pixels;
+    s += e - b;
+  }
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gmmsp_last_error(void) { return g_err.c_str(); }
+
+int gmmsp_grid(const gmmsp_params* params, gmmsp_grid_info* out) { return grid_of(params, out); }
+
+int gmmsp_workspace_bytes(int32_t n_images, const gmmsp_params* params, size_t* bytes) {
+  if (!bytes) return fail(GMMSP_E_INVAL, "null pointer");
+  Layout L;
+  int rc = plan(n_images, params, &L, nullptr);
+  if (rc) return rc;
+  *bytes = L.total;
+  return GMMSP_OK;
+}
+
+int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_dev,
+                 size_t workspace_bytes, void* stream, gmmsp_handle** out) {
+  if (!out || !workspace_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  *out = nullptr;
+  if (((uintptr_t)workspace_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
+  Layout L;
+  std::vector<ImgDesc> descs;
+  int rc = plan(n_images, params, &L, &descs);
+  if (rc) return rc;
+  if (workspace_bytes < L.total)
+    return fail(GMMSP_E_SIZE, "workspace %zu bytes < %zu needed", workspace_bytes, L.total);
+
+  std::vector<CellDesc> cells;
+  std::vector<SpDesc> sps;
+  cells.reserve(L.n_cell);
+  sps.reserve(L.n_sp);
+  for (int32_t b = 0; b < n_images; ++b) {
+    const ImgDesc& d = descs[b];
+    for (int cy = 0; cy < d.ncy; ++cy)
+      for (int cx = 0; cx < d.ncx; ++cx) cells.push_back(CellDesc{b, cx, cy, 0});
+    for (int ky = 0; ky < d.ny; ++ky)
+      for (int kx = 0; kx < d.nx; ++kx) sps.push_back(SpDesc{b, kx, ky, 0});
+  }
+  gmmsp_handle* h = new (std::nothrow) gmmsp_handle();
+  if (!h) return fail(GMMSP_E_INVAL, "out of host memory");
+  char* base = (char*)workspace_dev;
+  h->n_img = n_images;
+  h->n_pix = L.n_pix;
+  h->img = descs;
+  for (const ImgDesc& d : descs)  // sum_i |K_i| = sum_k |I_k|, a product of axis sums
+    h->pairs.push_back(window_extent_sum(d.W, d.vx, d.nx) * window_extent_sum(d.H, d.vy, d.ny));
+  DevPtrs& P = h->P;
+  P.img = (const ImgDesc*)(base + L.img);
+  P.state = (ImgState*)(base + L.state);
+  P.ll_hist = (double*)(base + L.ll_hist);
+  P.cell = (const CellDesc*)(base + L.cell);
+  P.sp = (const SpDesc*)(base + L.sp);
+  P.theta = (double*)(base + L.theta);
+  P.rec = (float*)(base + L.rec);
+  P.part = (double*)(base + L.part);
+  P.n_done = (int32_t*)(base + L.n_done);
+  P.n_img = n_images;
+  P.n_cell = L.n_cell;
+  P.n_sp = L.n_sp;
+
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)P.cell, cells.data(), sizeof(CellDesc) * cells.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)P.sp, sps.data(), sizeof(SpDesc) * sps.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_clear_records(P, s);
+  if (e == hipSuccess) e = launch_reset_state(P, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "gmmsp_create");
+  }
+  *out = h;
+  return GMMSP_OK;
+}
+
+int gmmsp_destroy(gmmsp_handle* h) {
+  delete h;
+  return GMMSP_OK;
+}
+
+int gmmsp_batch_info(const gmmsp_handle* h, int32_t* n_images, int64_t* n_pixels,
+                     int64_t* n_superpixels) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (n_images) *n_images = h->n_img;
+  if (n_pixels) *n_pixels = h->n_pix;
+  if (n_superpixels) *n_superpixels = h->P.n_sp;
+  return GMMSP_OK;
+}
+
+int gmmsp_image_grid(const gmmsp_handle* h, int32_t b, gmmsp_grid_info* out) {
+  if (!h || !out) return fail(GMMSP_E_INVAL, "null pointer");
+  if (b < 0 || b >= h->n_img) return fail(GMMSP_E_INVAL, "image %d out of range", b);
+  const ImgDesc& d = h->img[b];
+  *out = gmmsp_grid_info{d.vx, d.vy, d.nx, d.ny, d.K, d.ncx, d.ncy};
+  return GMMSP_OK;
+}
+
+int gmmsp_init_seeds(gmmsp_handle* h, const float* lab_dev, void* stream) {
+  if (!h || !lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_init_seeds");
+  h->initialised = true;
+  return GMMSP_OK;
+}
+
+int gmmsp_set_params_dev(gmmsp_handle* h, const double* theta_dev, void* stream) {
+  if (!h || !theta_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_set_params(h->P, theta_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_set_params_dev");
+  h->initialised = true;
+  return GMMSP_OK;
+}
+
+int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
+  if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  // stage the rows in the partials area, which the next pass overwrites anyway
+  const size_t bytes = sizeof(double) * kThetaRow * (size_t)h->P.n_sp;
+  if (bytes > sizeof(double) * kPartStride * (size_t)h->P.n_cell)
+    return fail(GMMSP_E_SIZE, "staging area too small");
+  hipError_t e = hipMemcpyAsync(h->P.part, theta_host, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_set_params(h->P, h->P.part, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_set_params");
+  h->initialised = true;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
+  if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(theta_host, h->P.theta, sizeof(double) * kThetaRow * (size_t)h->P.n_sp,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_get_params");
+  return GMMSP_OK;
+}
+
+int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, double rel_tol,
+                     int32_t* iters_host, void* stream) {
+  if (!h || !lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
+  if (max_iters < 0) return fail(GMMSP_E_INVAL, "max_iters < 0");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<ImgState> st(h->n_img);
+  hipError_t e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate");
+  int32_t tmax = 0;
+  for (const ImgState& x : st) tmax = x.t > tmax ? x.t : tmax;
+  if ((int64_t)tmax + max_iters > kLLCap)
+    return fail(GMMSP_E_STATE, "more than %d passes since the last initialisation", kLLCap);
+  if (h->profile && (int32_t)h->ev.size() < 2 * max_iters) {
+    const size_t need = 2 * (size_t)max_iters;
+    while (h->ev.size() < need) {
+      hipEvent_t x;
+      e = hipEventCreate(&x);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      h->ev.push_back(x);
+    }
+  }
+  int32_t launched = 0;
+  for (int32_t it = 0; it < max_iters; ++it) {
+    if (h->profile) e = hipEventRecord(h->ev[2 * it], s);
+    if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
+    if (e == hipSuccess && h->profile) e = hipEventRecord(h->ev[2 * it + 1], s);
+    if (e == hipSuccess) e = launch_ll_update(h->P, rel_tol, s);
+    if (e == hipSuccess) e = launch_finalize(h->P, s);
+    if (e != hipSuccess) return hip_fail(e, "em pass");
+    ++launched;
+    if (rel_tol > 0.0) {
+      int32_t n_done = 0;
+      e = hipMemcpyAsync(&n_done, h->P.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "em convergence check");
+      if (n_done >= h->n_img) break;
+    }
+  }
+  if (h->profile) {
+    std::vector<ImgState> st2(h->n_img);
+    e = hipMemcpyAsync(st2.data(), h->P.state, sizeof(ImgState) * h->n_img, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate profile");
+    for (int32_t it = 0; it < launched; ++it) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, h->ev[2 * it], h->ev[2 * it + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      h->prof_ms += ms;
+    }
+    h->prof_launches += launched;
+    for (int32_t b = 0; b < h->n_img; ++b) {
+      const int64_t evals = st2[b].t - st[b].t;  // E-steps that image b took part in
+      h->prof_pix += evals * (int64_t)h->img[b].W * h->img[b].H;
+      h->prof_pairs += evals * h->pairs[b];
+    }
+  }
+  if (iters_host) {
+    e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate");
+    for (int32_t b = 0; b < h->n_img; ++b) iters_host[b] = st[b].iters;
+  } else {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate");
+  }
+  return GMMSP_OK;
+}
+
+int gmmsp_ll_history(gmmsp_handle* h, int32_t b, double* out_host, int32_t cap, int32_t* n,
+                     void* stream) {
+  if (!h || !out_host || !n) return fail(GMMSP_E_INVAL, "null pointer");
+  if (b < 0 || b >= h->n_img) return fail(GMMSP_E_INVAL, "image %d out of range", b);
+  hipStream_t s = (hipStream_t)stream;
+  ImgState st;
+  hipError_t e = hipMemcpyAsync(&st, h->P.state + b, sizeof(st), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ll_history");
+  int32_t cnt = st.t < kLLCap ? st.t : kLLCap;
+  if (cnt > cap) cnt = cap;
+  if (cnt > 0) {
+    e = hipMemcpyAsync(out_host, h->P.ll_hist + (size_t)b * kLLCap, sizeof(double) * cnt,
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_ll_history");
+  }
+  *n = cnt;
+  return GMMSP_OK;
+}
+
+int gmmsp_label(gmmsp_handle* h, const float* lab_dev, int32_t* labels_dev, double* ll_host,
+                void* stream) {
+  if (!h || !lab_dev || !labels_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_label(h->P, lab_dev, labels_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_label");
+  if (ll_host) {
+    std::vector<ImgState> st(h->n_img);
+    e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_label");
+    for (int32_t b = 0; b < h->n_img; ++b) ll_host[b] = st[b].ll_final;
+  }
+  return GMMSP_OK;
+}
+
+int gmmsp_export_responsibilities(gmmsp_handle* h, const float* lab_dev, float* R_dev,
+                                  void* stream) {
+  if (!h || !lab_dev || !R_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
+  hipError_t e = launch_export_R(h->P, lab_dev, R_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_export_responsibilities");
+  return GMMSP_OK;
+}
+
+int gmmsp_profile_enable(gmmsp_handle* h, int32_t enable) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  h->profile = enable != 0;
+  return GMMSP_OK;
+}
+
+int gmmsp_profile_read(gmmsp_handle* h, double* estep_ms, int32_t* launches, int64_t* pixel_evals,
+                       int64_t* pair_evals, int32_t reset) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (estep_ms) *estep_ms = h->prof_ms;
+  if (launches) *launches = h->prof_launches;
+  if (pixel_evals) *pixel_evals = h->prof_pix;
+  if (pair_evals) *pair_evals = h->prof_pairs;
+  if (reset) {
+    h->prof_ms = 0.0;
+    h->prof_launches = 0;
+    h->prof_pix = 0;
+    h->prof_pairs = 0;
+  }
+  return GMMSP_OK;
+}
+
+int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream) {
+  if (!h || !cand_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
+  hipError_t e = launch_export_candidates(h->P, cand_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_export_candidates");
+  return GMMSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal layout shared by the host API (gmmsp_api.cpp) and the kernels
+// (gmmsp_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime.h>
+
+namespace gmmsp {
+
+constexpr int kSlots = 9;          // |K_i| <= 9: neighbour slots (dx, dy) in {-1,0,1}^2
+constexpr int kStats = 13;         // N, S1 (5), S2 (xx xy yy LL aa ab bb)
+constexpr int kPartStride = 120;   // doubles per cell: 9 x 13 statistics, [117] = LL
+constexpr int kLLSlot = 117;
+constexpr int kRecFloats = 16;     // floats per cell-slot record
+constexpr int kThetaRow = 13;      // doubles per superpixel in the FP64 master
+constexpr int kLLCap = 4096;       // log-likelihood history entries per image
+constexpr int kCellsPerBlock = 4;  // one 64-lane wave per cell, 4 waves per block
+
+// Cell-slot record: the parameters of the superpixel in slot s of cell c, in
+// float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
+// relative to the cell origin with colour (L, a, b):
+//   t1 = f[0] xr + f[1] yr + f[3],  t2 = f[2] yr + f[4],
+//   w  = f[5] L + f[6],
+//   u1 = f[7] a + f[8] b + f[10],   u2 = f[9] b + f[11],
+//   l  = f[12] - t1^2 - t2^2 - w^2 - u1^2 - u2^2 = log2 p(z; theta_k) - cmax2
+// and f[13..15] = (mu_L, mu_a, mu_b) rounded to float32, the colour origin of
+// the statistics.  An empty slot has f[12] = -inf and zeros elsewhere.
+enum RecField {
+  R_L11 = 0, R_L12 = 1, R_L22 = 2, R_O1 = 3, R_O2 = 4, R_SL = 5, R_OL = 6,
+  R_A11 = 7, R_A12 = 8, R_A22 = 9, R_O3 = 10, R_O4 = 11, R_C = 12,
+  R_ML = 13, R_MA = 14, R_MB = 15
+};
+
+// Statistic index inside a cell-slot partial.  Spatial moments are taken about
+// the cell origin, colour moments about the slot's float32 record mean.
+enum StatField {
+  S_N = 0, S_X = 1, S_Y = 2, S_L = 3, S_A = 4, S_B = 5,
+  S_XX = 6, S_XY = 7, S_YY = 8, S_LL = 9, S_AA = 10, S_AB = 11, S_BB = 12
+};
+
+struct ImgDesc {            // 96 bytes
+  int32_t W, H, vx, vy;
+  int32_t nx, ny, ncx, ncy;
+  int64_t pix_off;          // first pixel of the image in the packed batch
+  int32_t cell_off;         // first cell of the image in batch cell order
+  int32_t sp_off;           // first superpixel of the image in batch order
+  int32_t K, ncells;
+  double eps_s, eps_c, lam, n_min;
+  double lncmax;            // ln of the largest density the floors allow
+};
+
+struct ImgState {           // 32 bytes
+  int32_t t;                // passes evaluated since the last initialisation
+  int32_t done;             // 1 once the stop rule held
+  int32_t iters;            // M-steps applied
+  int32_t pad;
+  double ll_final;          // L(theta) of the last labelling pass
+  double pad2[2];
+};
+
+struct CellDesc { int32_t img, cx, cy, pad; };
+struct SpDesc { int32_t img, kx, ky, pad; };
+
+struct DevPtrs {
+  const ImgDesc* img;
+  ImgState* state;
+  double* ll_hist;          // [n_img][kLLCap]
+  const CellDesc* cell;
+  const SpDesc* sp;
+  double* theta;            // [n_sp][kThetaRow] FP64 master
+  float* rec;               // [n_cell][9][kRecFloats]
+  double* part;             // [n_cell][kPartStride]
+  int32_t* n_done;          // images that have stopped
+  int32_t n_img, n_cell, n_sp;
+};
+
+// Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s);
+hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s);
+hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s);
+hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s);
+hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s);
+hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s);
+hipError_t launch_finalize(const DevPtrs& P, hipStream_t s);
+hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s);
+hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s);
+hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
+
+}  // namespace gmmsp

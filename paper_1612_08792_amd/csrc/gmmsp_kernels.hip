@@ -1,0 +1,564 @@
+// HIP kernels (gfx950) of the GMM superpixel EM: E-step with fused M-step
+// statistics, log-likelihood reduction with the stop rule, per-superpixel
+// gather and FP64 shape control, initialisation and labelling.
+//
+// Work decomposition.  The image is cut into v_x x v_y pixel cells (plus the
+// partial remainder column / row).  All pixels of a cell share the same
+// candidate set K_i: the superpixels of the 3 x 3 neighbouring seed cells
+// (Eq. Ik), so one 64-lane wave owns one cell, reads its nine cell-slot records
+// with scalar loads, evaluates the E-step of each pixel in registers and keeps
+// the 9 x 13 sufficient statistics of the M-step in registers.  A butterfly
+// reduce-scatter across the wave leaves two totals per lane, written in FP64 as
+// the cell's partials.  Superpixel k then sums the partials of the (at most)
+// nine cells of its window I_k in a fixed order: no atomics, bitwise
+// repeatable.
+#include "gmmsp_internal.h"
+
+#include <math.h>
+
+namespace gmmsp {
+
+#define AS4 __attribute__((address_space(4)))
+
+// Uniform reads through the constant address space compile to scalar loads.
+template <typename T>
+__device__ __forceinline__ const AS4 T* cptr(const T* p) {
+  return (const AS4 T*)(p);
+}
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLn2Pi = 1.8378770664093454836;
+
+// ---------------------------------------------------------------------------
+// FP64 shape control of one symmetric 2x2 block [[a, b], [b, c]]
+// (Eqs. eigdecs, mlams, eigdecrs and their colour counterparts): both
+// eigenvalues floored at eps, the block rebuilt on the same eigenvectors.
+// ---------------------------------------------------------------------------
+struct Sym2 {
+  double a, b, c, det;
+};
+
+__device__ inline Sym2 clamp2(double a, double b, double c, double eps) {
+  const double h = 0.5 * (a - c);
+  const double r = sqrt(h * h + b * b);
+  const double m = 0.5 * (a + c);
+  const double l1 = m + r;  // larger eigenvalue
+  const double l2 = m - r;  // smaller eigenvalue
+  Sym2 o;
+  if (l2 >= eps) {
+    o.a = a;
+    o.b = b;
+    o.c = c;
+    o.det = a * c - b * b;
+    return o;
+  }
+  const double l1c = fmax(l1, eps);
+  if (r > 0.0) {
+    // S~ = eps I + (l1c - eps) v v^T, v v^T = (S - l2 I) / (l1 - l2)
+    const double inv = 1.0 / (2.0 * r);
+    const double d = l1c - eps;
+    o.a = eps + d * ((h + r) * inv);
+    o.b = d * (b * inv);
+    o.c = eps + d * ((r - h) * inv);
+  } else {
+    o.a = l1c;
+    o.b = 0.0;
+    o.c = l1c;
+  }
+  o.det = l1c * eps;
+  return o;
+}
+
+// FP64 parameters of one superpixel after shape control.
+struct SpTheta {
+  double mx, my, mL, ma, mb;          // absolute mean
+  double sxx, sxy, syy, sLL, saa, sab, sbb;
+  double det_s, det_ab;               // determinants of the 2x2 blocks
+};
+
+__device__ inline void store_theta_row(double* row, const SpTheta& q, double mass) {
+  row[0] = q.mx;  row[1] = q.my;  row[2] = q.mL;  row[3] = q.ma;  row[4] = q.mb;
+  row[5] = q.sxx; row[6] = q.sxy; row[7] = q.syy; row[8] = q.sLL;
+  row[9] = q.saa; row[10] = q.sab; row[11] = q.sbb; row[12] = mass;
+}
+
+// Write the float32 cell-slot records of superpixel (kx, ky) into the (up to)
+// nine cells whose candidate sets contain it.
+__device__ inline void write_records(const DevPtrs& P, const ImgDesc& I, int kx, int ky,
+                                     const SpTheta& q) {
+  const double s2 = sqrt(0.5 * kLog2e);  // l in log2 units: l = c - |whitened d|^2
+  // spatial block: P_s = Sigma_s^-1, factored as t1^2 + t2^2
+  const double l11 = s2 * sqrt(q.syy / q.det_s);
+  const double l12 = -s2 * q.sxy / sqrt(q.det_s * q.syy);
+  const double l22 = s2 / sqrt(q.syy);
+  const double sL = s2 / sqrt(q.sLL);
+  const double a11 = s2 * sqrt(q.sbb / q.det_ab);
+  const double a12 = -s2 * q.sab / sqrt(q.det_ab * q.sbb);
+  const double a22 = s2 / sqrt(q.sbb);
+  const double lndet = log(q.det_s) + log(q.sLL) + log(q.det_ab);
+  const double c = kLog2e * (-2.5 * kLn2Pi - 0.5 * lndet - I.lncmax);
+  const float fL = (float)q.mL, fa = (float)q.ma, fb = (float)q.mb;
+  const double oL = -sL * q.mL;
+  const double o3 = -(a11 * q.ma + a12 * q.mb);
+  const double o4 = -a22 * q.mb;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int cx = kx - dx, cy = ky - dy;
+      if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) continue;
+      const int slot = 3 * (dy + 1) + (dx + 1);
+      const double mxs = q.mx - (double)cx * I.vx;
+      const double mys = q.my - (double)cy * I.vy;
+      float4* dst = reinterpret_cast<float4*>(
+          P.rec + ((size_t)(I.cell_off + cy * I.ncx + cx) * kSlots + slot) * kRecFloats);
+      dst[0] = make_float4((float)l11, (float)l12, (float)l22, (float)(-(l11 * mxs + l12 * mys)));
+      dst[1] = make_float4((float)(-l22 * mys), (float)sL, (float)oL, (float)a11);
+      dst[2] = make_float4((float)a12, (float)a22, (float)o3, (float)o4);
+      dst[3] = make_float4((float)c, fL, fa, fb);
+    }
+  }
+}
+
+__device__ inline SpTheta theta_from_row(const double* row, const ImgDesc& I) {
+  SpTheta q;
+  q.mx = row[0]; q.my = row[1]; q.mL = row[2]; q.ma = row[3]; q.mb = row[4];
+  const Sym2 s = clamp2(row[5], row[6], row[7], I.eps_s);
+  const Sym2 ab = clamp2(row[9], row[10], row[11], I.eps_c);
+  q.sxx = s.a; q.sxy = s.b; q.syy = s.c; q.det_s = s.det;
+  q.sLL = fmax(row[8], I.eps_c);
+  q.saa = ab.a; q.sab = ab.b; q.sbb = ab.c; q.det_ab = ab.det;
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_clear_records(float* rec, size_t n_rec) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_rec) return;
+  float4* d = reinterpret_cast<float4*>(rec + i * kRecFloats);
+  d[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+  d[1] = d[0];
+  d[2] = d[0];
+  d[3] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_reset_state(DevPtrs P) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b == 0) *P.n_done = 0;
+  if (b >= P.n_img) return;
+  ImgState* st = P.state + b;
+  st->t = 0;
+  st->done = 0;
+  st->iters = 0;
+  st->ll_final = 0.0;
+}
+
+// Sec. III-C: mu_k = z_j at the seed pixel, Sigma_s = diag(v_x^2, v_y^2),
+// colour variances lambda^2.
+__global__ __launch_bounds__(256) void k_init_seeds(DevPtrs P, const float* __restrict__ lab) {
+  const int sp = blockIdx.x * 256 + threadIdx.x;
+  if (sp >= P.n_sp) return;
+  const SpDesc d = P.sp[sp];
+  const ImgDesc I = P.img[d.img];
+  const int x = d.kx * I.vx + I.vx / 2;
+  const int y = d.ky * I.vy + I.vy / 2;
+  const float* px = lab + 3 * (I.pix_off + (int64_t)y * I.W + x);
+  SpTheta q;
+  q.mx = x; q.my = y; q.mL = px[0]; q.ma = px[1]; q.mb = px[2];
+  const double l2 = I.lam * I.lam;
+  q.sxx = (double)I.vx * I.vx; q.sxy = 0.0; q.syy = (double)I.vy * I.vy;
+  q.sLL = l2; q.saa = l2; q.sab = 0.0; q.sbb = l2;
+  q.det_s = q.sxx * q.syy;
+  q.det_ab = l2 * l2;
+  store_theta_row(P.theta + (size_t)sp * kThetaRow, q, 0.0);
+  write_records(P, I, d.kx, d.ky, q);
+}
+
+__global__ __launch_bounds__(256) void k_set_params(DevPtrs P, const double* __restrict__ rows) {
+  const int sp = blockIdx.x * 256 + threadIdx.x;
+  if (sp >= P.n_sp) return;
+  const SpDesc d = P.sp[sp];
+  const ImgDesc I = P.img[d.img];
+  const double* row = rows + (size_t)sp * kThetaRow;
+  const SpTheta q = theta_from_row(row, I);
+  store_theta_row(P.theta + (size_t)sp * kThetaRow, q, row[12]);
+  write_records(P, I, d.kx, d.ky, q);
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell E-step kernel
+// ---------------------------------------------------------------------------
+
+enum CellMode { M_STATS = 0, M_LABEL = 1, M_EXPORT_R = 2, M_EXPORT_CAND = 3 };
+
+// log2 p(z; theta_k) - cmax2 for the record at f (Eq. gaussian, block diagonal)
+__device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, float L,
+                                        float A, float B) {
+  const float t1 = fmaf(f[R_L11], xr, fmaf(f[R_L12], yr, f[R_O1]));
+  const float t2 = fmaf(f[R_L22], yr, f[R_O2]);
+  const float w = fmaf(f[R_SL], L, f[R_OL]);
+  const float u1 = fmaf(f[R_A11], A, fmaf(f[R_A12], B, f[R_O3]));
+  const float u2 = fmaf(f[R_A22], B, f[R_O4]);
+  float l = fmaf(-t1, t1, f[R_C]);
+  l = fmaf(-t2, t2, l);
+  l = fmaf(-w, w, l);
+  l = fmaf(-u1, u1, l);
+  l = fmaf(-u2, u2, l);
+  return l;
+}
+
+// One step of the butterfly reduce-scatter: N values in, ceil(N/2) out.  Lanes
+// with (lane & MASK) == 0 keep the even entries summed with their partner's,
+// the others the odd ones; after the six steps lane l holds the wave totals of
+// entries bitrev6(l) and 64 + bitrev6(l).
+template <int N, int MASK, int CAP>
+__device__ __forceinline__ void bfly(float (&v)[CAP], int lane) {
+  const bool hi = (lane & MASK) != 0;
+  if (N & 1) v[N] = 0.f;  // odd count: the pair partner of the last entry is zero
+#pragma unroll
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
+    const float a = v[2 * i];
+    const float b = v[2 * i + 1];
+    const float send = hi ? a : b;
+    const float keep = hi ? b : a;
+    v[i] = keep + __shfl_xor(send, MASK, 64);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_cells(DevPtrs P, const float* __restrict__ lab,
+                                               int32_t* __restrict__ out_i,
+                                               float* __restrict__ out_f) {
+  const int lane = threadIdx.x & 63;
+  const int cell = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * kCellsPerBlock + (threadIdx.x >> 6)));
+  if (cell >= P.n_cell) return;
+  const AS4 CellDesc* cdp = cptr(P.cell) + cell;
+  const int b = cdp->img, ccx = cdp->cx, ccy = cdp->cy;
+  const AS4 ImgDesc* Ip = cptr(P.img) + b;
+  if (MODE == M_STATS && cptr(P.state)[b].done) return;
+  const int W = Ip->W, H = Ip->H, vx = Ip->vx, vy = Ip->vy;
+  const int x0 = ccx * vx, y0 = ccy * vy;
+  const int w = min(vx, W - x0), h = min(vy, H - y0);
+  const int npix = w * h;
+  const int64_t pix0 = Ip->pix_off + (int64_t)y0 * W + x0;
+  const float* img = lab + 3 * pix0;
+  const AS4 float* rec = cptr(P.rec) + (size_t)cell * (kSlots * kRecFloats);
+
+  if (MODE == M_EXPORT_CAND) {
+    const int nx = Ip->nx, ny = Ip->ny;
+    for (int p = lane; p < npix; p += 64) {
+      const int row = p / w, col = p - row * w;
+      int32_t* dst = out_i + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int kx = ccx + (s % 3) - 1, ky = ccy + (s / 3) - 1;
+        const bool idx_ok = kx >= 0 && kx < nx && ky >= 0 && ky < ny;
+        const bool rec_ok = rec[s * kRecFloats + R_C] != -INFINITY;
+        dst[s] = (idx_ok != rec_ok) ? -2 : (idx_ok ? ky * nx + kx : -1);
+      }
+    }
+    return;
+  }
+
+  // 117 statistics plus one zero pad, so every butterfly step reads pairs
+  float acc[kSlots * kStats + 1];
+  if (MODE == M_STATS) {
+#pragma unroll
+    for (int i = 0; i < kSlots * kStats + 1; ++i) acc[i] = 0.f;
+  }
+  float llacc = 0.f;
+
+  // lane -> (row, col) inside the cell, advanced by 64 pixels per iteration
+  int row = lane / w, col = lane - (lane / w) * w;
+  const int drow = 64 / w, dcol = 64 - (64 / w) * w;
+
+  for (int p = lane; p < npix; p += 64) {
+    const float* px = img + 3 * (row * W + col);
+    const float L = px[0], A = px[1], B = px[2];
+    const float xr = (float)col, yr = (float)row;
+
+    float e[kSlots];
+    float sum = 0.f;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      e[s] = __builtin_amdgcn_exp2f(eval_l(rec + s * kRecFloats, xr, yr, L, A, B));
+      sum += e[s];
+    }
+    float shift = 0.f;
+    if (sum < 0x1p-100f) {
+      // every candidate is far away: subtract the largest exponent first
+      float lv[kSlots];
+      float m = -INFINITY;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        lv[s] = eval_l(rec + s * kRecFloats, xr, yr, L, A, B);
+        m = fmaxf(m, lv[s]);
+      }
+      sum = 0.f;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        e[s] = __builtin_amdgcn_exp2f(lv[s] - m);
+        sum += e[s];
+      }
+      shift = m;
+    }
+    const float inv = __builtin_amdgcn_rcpf(sum);
+    llacc += __builtin_amdgcn_logf(sum) + shift;
+
+    if (MODE == M_STATS) {
+      const float xx = xr * xr, xy = xr * yr, yy = yr * yr;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const AS4 float* f = rec + s * kRecFloats;
+        float* a = acc + s * kStats;
+        const float R = e[s] * inv;
+        a[S_N] += R;
+        a[S_X] = fmaf(R, xr, a[S_X]);
+        a[S_Y] = fmaf(R, yr, a[S_Y]);
+        a[S_XX] = fmaf(R, xx, a[S_XX]);
+        a[S_XY] = fmaf(R, xy, a[S_XY]);
+        a[S_YY] = fmaf(R, yy, a[S_YY]);
+        const float dL = L - f[R_ML];
+        const float da = A - f[R_MA];
+        const float db = B - f[R_MB];
+        const float rL = R * dL;
+        a[S_L] += rL;
+        a[S_LL] = fmaf(rL, dL, a[S_LL]);
+        const float ra = R * da;
+        a[S_A] += ra;
+        a[S_AA] = fmaf(ra, da, a[S_AA]);
+        a[S_AB] = fmaf(ra, db, a[S_AB]);
+        const float rb = R * db;
+        a[S_B] += rb;
+        a[S_BB] = fmaf(rb, db, a[S_BB]);
+      }
+    } else if (MODE == M_LABEL) {
+      int best = 0;
+      float be = e[0];
+#pragma unroll
+      for (int s = 1; s < kSlots; ++s) {
+        if (e[s] > be) {
+          be = e[s];
+          best = s;
+        }
+      }
+      const int kx = ccx + (best % 3) - 1, ky = ccy + (best / 3) - 1;
+      out_i[pix0 + (int64_t)row * W + col] = ky * Ip->nx + kx;
+    } else if (MODE == M_EXPORT_R) {
+      float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) dst[s] = e[s] * inv;
+    }
+
+    col += dcol;
+    row += drow;
+    if (col >= w) {
+      col -= w;
+      row += 1;
+    }
+  }
+
+  if (MODE == M_STATS || MODE == M_LABEL) {
+    // cell log-likelihood: sum_i ln sum_k p = ln2 (sum_i l2_i) + npix ln(cmax)
+    double ll = (double)llacc;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
+    double* part = P.part + (size_t)cell * kPartStride;
+    if (lane == 0) part[kLLSlot] = kLn2 * ll + (double)npix * Ip->lncmax;
+  }
+  if (MODE == M_STATS) {
+    bfly<117, 32>(acc, lane);
+    bfly<59, 16>(acc, lane);
+    bfly<30, 8>(acc, lane);
+    bfly<15, 4>(acc, lane);
+    bfly<8, 2>(acc, lane);
+    bfly<4, 1>(acc, lane);
+    const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
+    double* part = P.part + (size_t)cell * kPartStride;
+    part[r] = (double)acc[0];
+    if (64 + r < kSlots * kStats) part[64 + r] = (double)acc[1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L(theta^t) per image and the stop rule; one block per image
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const ImgDesc* I = P.img + b;
+  ImgState* st = P.state + b;
+  const int done = st->done;
+  if (!final_pass && done) return;
+  const int ncells = I->ncells;
+  const double* part = P.part + (size_t)I->cell_off * kPartStride + kLLSlot;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < ncells; c += 256) s += part[(size_t)c * kPartStride];
+  red[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double L = red[0];
+  if (final_pass) {
+    st->ll_final = L;
+    return;
+  }
+  const int t = st->t;
+  double* hist = P.ll_hist + (size_t)b * kLLCap;
+  if (t < kLLCap) hist[t] = L;
+  bool conv = false;
+  if (rel_tol > 0.0 && t >= 1) {
+    const double Lp = hist[t - 1];
+    conv = fabs(L - Lp) <= rel_tol * fabs(Lp);
+  }
+  if (conv) {
+    st->done = 1;
+    atomicAdd(P.n_done, 1);
+  } else {
+    st->iters = t + 1;
+  }
+  st->t = t + 1;
+}
+
+// ---------------------------------------------------------------------------
+// M-step: per superpixel gather of the window's cell partials in a fixed
+// order, mean (Eq. UpdateMu), block covariances (Eqs. UpdateSigS, UpdateSigC)
+// and shape control (Eqs. eigdecs .. eigdecrc), all in FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
+  const int sp = blockIdx.x * 256 + threadIdx.x;
+  if (sp >= P.n_sp) return;
+  const SpDesc d = P.sp[sp];
+  if (P.state[d.img].done) return;
+  const ImgDesc I = P.img[d.img];
+  double acc[kStats];
+#pragma unroll
+  for (int j = 0; j < kStats; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int cx = d.kx - dx, cy = d.ky - dy;
+      if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) continue;
+      const int slot = 3 * (dy + 1) + (dx + 1);
+      const double* q = P.part + (size_t)(I.cell_off + cy * I.ncx + cx) * kPartStride + slot * kStats;
+      // move the spatial moments from the cell origin to the superpixel's
+      // own cell origin: x' = x + ox with ox = (cx - kx) v_x
+      const double ox = (double)(-dx) * I.vx, oy = (double)(-dy) * I.vy;
+      const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
+      acc[S_N] += n;
+      acc[S_X] += sx + ox * n;
+      acc[S_Y] += sy + oy * n;
+      acc[S_L] += q[S_L];
+      acc[S_A] += q[S_A];
+      acc[S_B] += q[S_B];
+      acc[S_XX] += q[S_XX] + 2.0 * ox * sx + ox * ox * n;
+      acc[S_XY] += q[S_XY] + ox * sy + oy * sx + ox * oy * n;
+      acc[S_YY] += q[S_YY] + 2.0 * oy * sy + oy * oy * n;
+      acc[S_LL] += q[S_LL];
+      acc[S_AA] += q[S_AA];
+      acc[S_AB] += q[S_AB];
+      acc[S_BB] += q[S_BB];
+    }
+  }
+  double* row = P.theta + (size_t)sp * kThetaRow;
+  const double N = acc[S_N];
+  if (!(N >= I.n_min)) {
+    row[12] = N;  // 0/0 guard: theta_k keeps its value
+    return;
+  }
+  const double iN = 1.0 / N;
+  const double mx = acc[S_X] * iN, my = acc[S_Y] * iN;
+  const double mL = acc[S_L] * iN, ma = acc[S_A] * iN, mb = acc[S_B] * iN;
+  SpTheta q;
+  q.mx = (double)d.kx * I.vx + mx;
+  q.my = (double)d.ky * I.vy + my;
+  // colour moments were taken about the float32 record mean
+  q.mL = (double)(float)row[2] + mL;
+  q.ma = (double)(float)row[3] + ma;
+  q.mb = (double)(float)row[4] + mb;
+  const Sym2 s = clamp2(acc[S_XX] * iN - mx * mx, acc[S_XY] * iN - mx * my,
+                        acc[S_YY] * iN - my * my, I.eps_s);
+  const Sym2 c = clamp2(acc[S_AA] * iN - ma * ma, acc[S_AB] * iN - ma * mb,
+                        acc[S_BB] * iN - mb * mb, I.eps_c);
+  q.sxx = s.a; q.sxy = s.b; q.syy = s.c; q.det_s = s.det;
+  q.sLL = fmax(acc[S_LL] * iN - mL * mL, I.eps_c);
+  q.saa = c.a; q.sab = c.b; q.sbb = c.c; q.det_ab = c.det;
+  store_theta_row(row, q, N);
+  write_records(P, I, d.kx, d.ky, q);
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(size_t n, unsigned per) {
+  return (unsigned)((n + per - 1) / per);
+}
+
+hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s) {
+  const size_t n = (size_t)P.n_cell * kSlots;
+  hipLaunchKernelGGL(k_clear_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, P.rec, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_state, dim3(blocks_for(P.n_img, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_params, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells<M_STATS>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256), 0,
+                     s, P, lab, (int32_t*)nullptr, (float*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, rel_tol, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256), 0,
+                     s, P, lab, labels, (float*)nullptr);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, 0.0, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells<M_EXPORT_R>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256),
+                     0, s, P, lab, (int32_t*)nullptr, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells<M_EXPORT_CAND>, dim3(blocks_for(P.n_cell, kCellsPerBlock)),
+                     dim3(256), 0, s, P, (const float*)nullptr, cand, (float*)nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace gmmsp

@@ -1,0 +1,171 @@
+"""Python front end of the gmmsp library: PyTorch supplies device memory and
+the stream, libgmmsp.so does every step of the method."""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GmmspGridInfo, GmmspParams, THETA_ROW, check, lib
+
+
+def make_params(W: int, H: int, K: int = 0, vx: int = 0, vy: int = 0, eps_s: float = 2.0,
+                eps_c: float = 8.0, lam: float = 8.0, cov_mode: int = 0,
+                n_min: float = 1e-3) -> GmmspParams:
+    return GmmspParams(W, H, K, vx, vy, eps_s, eps_c, lam, cov_mode, n_min)
+
+
+def grid(W: int, H: int, K: int = 0, vx: int = 0, vy: int = 0) -> GmmspGridInfo:
+    """Seed grid by Eqs. vxy and nxyK (host-only library call)."""
+    g = GmmspGridInfo()
+    check(lib().gmmsp_grid(byref(make_params(W, H, K, vx, vy)), byref(g)))
+    return g
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class GMMSP:
+    """A batch of images (one image is a batch of one) bound to a workspace.
+
+    ``sizes``: sequence of (W, H); ``K`` (or ``v``): one value for all images or
+    one per image.  Inputs are packed float32 Lab tensors on the device (image b
+    at pixel offset ``pix_off[b]``)."""
+
+    def __init__(self, sizes: Sequence[tuple], K=None, v=None, eps_s: float = 2.0,
+                 eps_c: float = 8.0, lam: float = 8.0, n_min: float = 1e-3,
+                 device="cuda"):
+        n = len(sizes)
+        Ks = K if isinstance(K, (list, tuple)) else [K] * n
+        vs = v if isinstance(v, (list, tuple)) else [v] * n
+        arr = (GmmspParams * n)()
+        for b, (W, H) in enumerate(sizes):
+            vb = vs[b]
+            vx, vy = (vb if isinstance(vb, (list, tuple)) else (vb, vb)) if vb else (0, 0)
+            arr[b] = make_params(W, H, Ks[b] or 0, vx, vy, eps_s, eps_c, lam, 0, n_min)
+        self.params = arr
+        self.n_images = n
+        self.device = torch.device(device)
+        nbytes = c_size_t(0)
+        check(lib().gmmsp_workspace_bytes(n, arr, byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        h = c_void_p()
+        check(lib().gmmsp_create(n, arr, c_void_p(_ptr(self.workspace)), nbytes.value,
+                                 c_void_p(self._stream()), byref(h)))
+        self.handle = h
+        ni, npx, nsp = c_int32(), c_int64(), c_int64()
+        check(lib().gmmsp_batch_info(h, byref(ni), byref(npx), byref(nsp)))
+        self.n_pixels = npx.value
+        self.n_superpixels = nsp.value
+        self.grids = []
+        for b in range(n):
+            g = GmmspGridInfo()
+            check(lib().gmmsp_image_grid(h, b, byref(g)))
+            self.grids.append(g)
+        self.sizes = [tuple(s) for s in sizes]
+        self.pix_off = np.concatenate([[0], np.cumsum([W * H for W, H in sizes])]).astype(np.int64)
+        self.sp_off = np.concatenate([[0], np.cumsum([g.K for g in self.grids])]).astype(np.int64)
+
+    # -- plumbing ------------------------------------------------------------
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _lab(self, lab: torch.Tensor) -> c_void_p:
+        if lab.dtype != torch.float32 or not lab.is_contiguous() or lab.device != self.device:
+            raise ValueError("lab must be a contiguous float32 tensor on the handle's device")
+        if lab.numel() != 3 * self.n_pixels:
+            raise ValueError(f"lab has {lab.numel()} floats, expected {3 * self.n_pixels}")
+        return c_void_p(_ptr(lab))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().gmmsp_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method ------------------------------------------------------------
+    def init_seeds(self, lab: torch.Tensor):
+        check(lib().gmmsp_init_seeds(self.handle, self._lab(lab), c_void_p(self._stream())))
+
+    def set_params(self, rows) -> None:
+        """theta rows (n_superpixels, 13): numpy (host) or a float64 device tensor."""
+        if isinstance(rows, torch.Tensor) and rows.device.type == "cuda":
+            if rows.dtype != torch.float64 or not rows.is_contiguous() or \
+                    rows.shape != (self.n_superpixels, THETA_ROW):
+                raise ValueError("theta must be a contiguous (n_sp, 13) float64 tensor")
+            check(lib().gmmsp_set_params_dev(self.handle, c_void_p(_ptr(rows)),
+                                             c_void_p(self._stream())))
+            return
+        a = np.ascontiguousarray(np.asarray(rows, dtype=np.float64))
+        if a.shape != (self.n_superpixels, THETA_ROW):
+            raise ValueError("theta must have shape (n_superpixels, 13)")
+        check(lib().gmmsp_set_params(self.handle, c_void_p(a.ctypes.data),
+                                     c_void_p(self._stream())))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty((self.n_superpixels, THETA_ROW), dtype=np.float64)
+        check(lib().gmmsp_get_params(self.handle, c_void_p(out.ctypes.data),
+                                     c_void_p(self._stream())))
+        return out
+
+    def em_iterate(self, lab: torch.Tensor, max_iters: int, rel_tol: float = 0.0) -> np.ndarray:
+        it = np.zeros(self.n_images, dtype=np.int32)
+        check(lib().gmmsp_em_iterate(self.handle, self._lab(lab), int(max_iters),
+                                     float(rel_tol), c_void_p(it.ctypes.data),
+                                     c_void_p(self._stream())))
+        return it
+
+    def ll_history(self, b: int = 0) -> np.ndarray:
+        out = np.empty(_lib.LL_CAP, dtype=np.float64)
+        n = c_int32()
+        check(lib().gmmsp_ll_history(self.handle, b, c_void_p(out.ctypes.data), _lib.LL_CAP,
+                                     byref(n), c_void_p(self._stream())))
+        return out[:n.value].copy()
+
+    def label(self, lab: torch.Tensor, labels: torch.Tensor | None = None, want_ll=True):
+        if labels is None:
+            labels = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
+        ll = np.zeros(self.n_images, dtype=np.float64)
+        check(lib().gmmsp_label(self.handle, self._lab(lab), c_void_p(_ptr(labels)),
+                                c_void_p(ll.ctypes.data) if want_ll else None,
+                                c_void_p(self._stream())))
+        return labels, ll
+
+    def export_responsibilities(self, lab: torch.Tensor) -> torch.Tensor:
+        R = torch.zeros((self.n_pixels, 9), dtype=torch.float32, device=self.device)
+        check(lib().gmmsp_export_responsibilities(self.handle, self._lab(lab),
+                                                  c_void_p(_ptr(R)), c_void_p(self._stream())))
+        return R
+
+    def export_candidates(self) -> torch.Tensor:
+        c = torch.full((self.n_pixels, 9), -3, dtype=torch.int32, device=self.device)
+        check(lib().gmmsp_export_candidates(self.handle, c_void_p(_ptr(c)),
+                                            c_void_p(self._stream())))
+        return c
+
+    def profile(self, enable: bool = True):
+        check(lib().gmmsp_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms, n, px, pr = c_double(), c_int32(), c_int64(), c_int64()
+        check(lib().gmmsp_profile_read(self.handle, byref(ms), byref(n), byref(px), byref(pr),
+                                       1 if reset else 0))
+        return dict(estep_ms=ms.value, launches=n.value, pixel_evals=px.value,
+                    pair_evals=pr.value)
+
+    # -- helpers -------------------------------------------------------------
+    def image_slice(self, b: int) -> slice:
+        return slice(int(self.pix_off[b]), int(self.pix_off[b + 1]))
+
+    def sp_slice(self, b: int) -> slice:
+        return slice(int(self.sp_off[b]), int(self.sp_off[b + 1]))

@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/gmmsp.h declares, computes the seed grid bit-exactly like the
+oracle and rejects bad arguments with the documented codes.  No GPU needed:
+nothing here launches a kernel."""
+import ctypes
+import os
+import re
+from ctypes import byref, c_size_t, c_void_p
+
+import numpy as np
+import pytest
+
+from oracle import gmm_oracle as O
+from paper_1612_08792_amd import _lib
+from paper_1612_08792_amd.gmmsp import make_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmmsp.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmmsp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.exported_symbols()) == names
+
+
+def test_params_struct_layout_matches_header():
+    # int32 W H K vx vy | pad | double eps_s eps_c lambda | int32 cov_mode | pad | double n_min
+    assert ctypes.sizeof(_lib.GmmspParams) == 64
+    assert _lib.GmmspParams.eps_s.offset == 24
+    assert _lib.GmmspParams.n_min.offset == 56
+
+
+def _grid(W, H, K=0, vx=0, vy=0):
+    g = _lib.GmmspGridInfo()
+    rc = _lib.lib().gmmsp_grid(byref(make_params(W, H, K, vx, vy)), byref(g))
+    return rc, g
+
+
+def test_grid_bit_exact_against_oracle():
+    rng = np.random.default_rng(1)
+    cases = [(481, 321, 400), (1920, 1080, 2000), (3840, 2160, 10000), (1, 1, 1),
+             (7, 3, 21), (5000, 1, 17)]
+    for _ in range(3000):
+        W = int(rng.integers(1, 6000))
+        H = int(rng.integers(1, 4000))
+        cases.append((W, H, int(rng.integers(1, W * H + 1))))
+    for W, H, K in cases:
+        rc, g = _grid(W, H, K)
+        try:
+            og = O.make_grid(W, H, K=K)
+        except ValueError:
+            assert rc == _lib.GMMSP_E_SIZE
+            continue
+        assert rc == 0
+        assert (g.vx, g.vy, g.nx, g.ny, g.K) == (og.vx, og.vy, og.nx, og.ny, og.K)
+        assert g.ncx == -(-W // og.vx) and g.ncy == -(-H // og.vy)
+
+
+def test_grid_explicit_spacing():
+    rc, g = _grid(60, 41, vx=12, vy=7)
+    og = O.make_grid(60, 41, vx=12, vy=7)
+    assert rc == 0 and (g.nx, g.ny, g.K, g.ncx, g.ncy) == (og.nx, og.ny, og.K, 5, 6)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 5, 1), _lib.GMMSP_E_INVAL),
+    ((5, 0, 1), _lib.GMMSP_E_INVAL),
+    ((5, 5, 0), _lib.GMMSP_E_INVAL),
+    ((5, 5, 26), _lib.GMMSP_E_INVAL),
+    ((5, 5, 0, -1, 2), _lib.GMMSP_E_INVAL),
+    ((5, 5, 0, 6, 2), _lib.GMMSP_E_SIZE),
+])
+def test_grid_error_codes(args, code):
+    rc, _ = _grid(*args)
+    assert rc == code
+    assert len(_lib.lib().gmmsp_last_error()) > 0
+
+
+def test_workspace_bytes_and_validation():
+    L = _lib.lib()
+    arr = (_lib.GmmspParams * 2)(make_params(481, 321, 400), make_params(640, 480, 512))
+    n = c_size_t(0)
+    assert L.gmmsp_workspace_bytes(2, arr, byref(n)) == 0
+    n1 = c_size_t(0)
+    assert L.gmmsp_workspace_bytes(1, arr, byref(n1)) == 0
+    assert n.value > n1.value > 154401 // 10
+    bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, cov_mode=1))
+    assert L.gmmsp_workspace_bytes(1, bad, byref(n)) == _lib.GMMSP_E_INVAL
+    bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, eps_c=0.0))
+    assert L.gmmsp_workspace_bytes(1, bad, byref(n)) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_workspace_bytes(0, arr, byref(n)) == _lib.GMMSP_E_INVAL
+
+
+def test_create_rejects_bad_arguments_before_any_device_work():
+    L = _lib.lib()
+    arr = (_lib.GmmspParams * 1)(make_params(481, 321, 400))
+    h = c_void_p()
+    assert L.gmmsp_create(1, arr, None, 1 << 20, None, byref(h)) == _lib.GMMSP_E_INVAL
+    # misaligned workspace pointer
+    assert L.gmmsp_create(1, arr, c_void_p(0x1001), 1 << 20, None, byref(h)) == _lib.GMMSP_E_INVAL
+    # too small a workspace
+    assert L.gmmsp_create(1, arr, c_void_p(0x1000), 16, None, byref(h)) == _lib.GMMSP_E_SIZE
+    assert L.gmmsp_em_iterate(None, None, 1, 0.0, None, None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_label(None, None, None, None, None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_init_seeds(None, None, None) == _lib.GMMSP_E_INVAL

@@ -1,0 +1,270 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+Tolerances are stated in tests/parity_helpers.py."""
+import hashlib
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gmm_oracle as O
+from paper_1612_08792_amd.gmmsp import GMMSP
+from parity_helpers import (assert_theta_close, label_agreement, oracle_margin,
+                            oracle_slots, theta_errors)
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def run_gpu(im, dev, T, K=None, v=None, rel_tol=0.0):
+    m = GMMSP([(im.W, im.H)], K=K if K is not None else (None if v else im.K), v=v, device=dev)
+    lab = im.lab.reshape(-1).to(dev)
+    m.init_seeds(lab)
+    iters = m.em_iterate(lab, T, rel_tol)
+    labels, ll = m.label(lab)
+    R = m.export_responsibilities(lab)
+    return dict(m=m, lab=lab, iters=iters, labels=labels.cpu().numpy(), ll_final=ll[0],
+                theta=m.get_params(), hist=m.ll_history(0), R=R.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# integer indexing: bit-exact
+# ---------------------------------------------------------------------------
+GRIDS = [(481, 321, 400, None), (62, 45, None, 10), (60, 41, None, (12, 7)),
+         (25, 31, None, 9), (13, 17, None, (13, 17)), (100, 9, None, 9),
+         (1, 1, 1, None), (3840, 2160, 10000, None)]
+
+
+@pytest.mark.parametrize("W,H,K,v", GRIDS)
+def test_candidate_indexing_bit_exact(dev, W, H, K, v):
+    say(f"candidates {W}x{H} K={K} v={v}")
+    lab = torch.zeros(W * H * 3, dtype=torch.float32, device=dev)
+    m = GMMSP([(W, H)], K=K, v=v, device=dev)
+    m.init_seeds(lab)
+    got = m.export_candidates().cpu().numpy().reshape(H, W, 9)
+    vx, vy = (v if isinstance(v, tuple) else (v, v)) if v else (None, None)
+    g = O.make_grid(W, H, K=K, vx=vx, vy=vy)
+    cand, _ = O.candidate_sets(g)
+    want = O.to_slots(g, cand, cand, fill=-1)
+    assert (got != -2).all(), "record validity disagrees with the slot index"
+    assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# initialisation and one EM step from an identical theta
+# ---------------------------------------------------------------------------
+def test_init_matches_oracle(dev):
+    im = synth.config1_image()
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    m.init_seeds(im.lab.reshape(-1).to(dev))
+    g = O.make_grid(im.W, im.H, K=im.K)
+    th = O.init_theta(g, O.features(im.lab.numpy()), O.Params())
+    np.testing.assert_array_equal(m.get_params()[:, :12], O.theta_to_rows(th)[:, :12])
+
+
+def test_one_step_parity_config1(dev):
+    say("one-step parity 481x321")
+    im = synth.config1_image()
+    g = O.make_grid(im.W, im.H, K=im.K)
+    res = O.run_em(im.lab.numpy(), g, max_iters=3)
+    rows = O.theta_to_rows(res["theta"])
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    lab = im.lab.reshape(-1).to(dev)
+    m.set_params(rows)
+    R = m.export_responsibilities(lab).cpu().numpy()
+    Ro = oracle_slots(g, res["cand"], res["R"])
+    assert np.abs(R - Ro).max() <= 1e-5
+    m.em_iterate(lab, 1)
+    L_gpu = m.ll_history(0)[0]
+    assert L_gpu == pytest.approx(res["ll_final"], rel=1e-7)
+    th1 = O.mstep(res["z"], g, res["R"], res["pos"], res["theta"], O.Params())
+    e = assert_theta_close(m.get_params(), O.theta_to_rows(th1), 1e-5, what="one step")
+    say("one-step errors", e)
+
+
+# ---------------------------------------------------------------------------
+# trajectories
+# ---------------------------------------------------------------------------
+def test_trajectory_config1_T10(dev):
+    say("trajectory 481x321 T=10")
+    im = synth.config1_image()
+    g = O.make_grid(im.W, im.H, K=im.K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=10)
+    out = run_gpu(im, dev, 10)
+    assert out["iters"][0] == 10
+    e = assert_theta_close(out["theta"], O.theta_to_rows(ref["theta"]), 1e-3, what="T=10")
+    Ro = oracle_slots(g, ref["cand"], ref["R"])
+    r_err = np.abs(out["R"] - Ro).max()
+    assert r_err <= 1e-4
+    agree, ties = label_agreement(out["labels"], ref["labels"].reshape(-1),
+                                  oracle_margin(ref["R"]))
+    assert agree >= 0.999
+    np.testing.assert_allclose(out["hist"], ref["ll_hist"], rtol=1e-6)
+    assert out["ll_final"] == pytest.approx(ref["ll_final"], rel=1e-6)
+    say("T=10 errors", e, "R", r_err, "labels", agree, "ties", ties)
+
+
+def test_trajectory_config2_T20_golden(dev):
+    say("trajectory 1920x1080 T=20 against stored oracle values")
+    gold = np.load(os.path.join(HERE, "golden", "cfg2_oracle.npz"))
+    im = synth.config2_image()
+    lab_np = im.lab.numpy()
+    digest = hashlib.sha256(np.ascontiguousarray(lab_np).tobytes()).hexdigest()
+    assert digest == str(gold["lab_sha256"]), "synthetic input differs from the stored one"
+    out = run_gpu(im, dev, 20)
+    e = assert_theta_close(out["theta"], gold["theta"], 1e-3, what="T=20")
+    pix = gold["sample_pix"]
+    r_err = np.abs(out["R"][pix] - gold["sample_R"]).max()
+    assert r_err <= 1e-4
+    agree, ties = label_agreement(out["labels"], gold["labels"].reshape(-1).astype(np.int32),
+                                  gold["margin"])
+    assert agree >= 0.999
+    np.testing.assert_allclose(out["hist"], gold["ll_hist"], rtol=1e-6)
+    say("T=20 errors", e, "R", r_err, "labels", agree, "ties", ties)
+
+
+def test_separated_blocks_exact_labels(dev):
+    for v, nbx, nby in [(6, 5, 4), (8, 4, 4), (11, 3, 5), (16, 9, 7)]:
+        im = synth.separated_blocks(v, nbx, nby)
+        out = run_gpu(im, dev, 4, v=v)
+        assert np.array_equal(out["labels"], im.regions.numpy().reshape(-1))
+        var = (v * v - 1) / 12.0
+        th = out["theta"]
+        for k in range(nbx * nby):
+            kx, ky = k % nbx, k // nbx
+            col = synth.BLOCK_PALETTE[(kx % 3) + 3 * (ky % 3)]
+            want = [kx * v + (v - 1) / 2, ky * v + (v - 1) / 2, *col]
+            np.testing.assert_allclose(th[k, :5], want, atol=1e-4)
+            np.testing.assert_allclose(th[k, 5:12], [var, 0, var, 8, 8, 0, 8], atol=1e-4 * var)
+
+
+def test_relative_tolerance_stop_matches_oracle(dev):
+    im = synth.voronoi_lab(320, 240, 19, 3.0, 77, 200)
+    g = O.make_grid(im.W, im.H, K=im.K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=60, rel_tol=1e-4)
+    out = run_gpu(im, dev, 60, rel_tol=1e-4)
+    assert abs(int(out["iters"][0]) - ref["iters"]) <= 1
+    n = min(len(out["hist"]), len(ref["ll_hist"]))
+    np.testing.assert_allclose(out["hist"][:n], ref["ll_hist"][:n], rtol=1e-6)
+    say("stop rule iters gpu", out["iters"][0], "oracle", ref["iters"])
+
+
+# ---------------------------------------------------------------------------
+# determinism, batching, edge cases
+# ---------------------------------------------------------------------------
+def test_bitwise_determinism(dev):
+    im = synth.config1_image()
+    a = run_gpu(im, dev, 5)
+    b = run_gpu(im, dev, 5)
+    assert np.array_equal(a["theta"], b["theta"])
+    assert np.array_equal(a["labels"], b["labels"])
+    assert np.array_equal(a["hist"], b["hist"])
+    assert np.array_equal(a["R"], b["R"])
+
+
+def test_batch_equals_single_images(dev):
+    ims = [synth.voronoi_lab(333, 217, 18, 3.0, 5, 150),
+           synth.voronoi_lab(97, 180, 6, 2.0, 6, 40),
+           synth.voronoi_lab(640, 481, 60, 4.0, 7, 512)]
+    sizes = [(im.W, im.H) for im in ims]
+    m = GMMSP(sizes, K=[im.K for im in ims], device=dev)
+    lab = synth.pack_batch(ims).to(dev)
+    m.init_seeds(lab)
+    iters = m.em_iterate(lab, 6)
+    assert list(iters) == [6, 6, 6]
+    labels, ll = m.label(lab)
+    th = m.get_params()
+    labels = labels.cpu().numpy()
+    for b, im in enumerate(ims):
+        one = run_gpu(im, dev, 6)
+        assert np.array_equal(th[m.sp_slice(b)], one["theta"])
+        assert np.array_equal(labels[m.image_slice(b)], one["labels"])
+        assert np.array_equal(m.ll_history(b), one["hist"])
+        assert ll[b] == one["ll_final"]
+
+
+@pytest.mark.parametrize("W,H,K,v", [(9, 9, 1, None), (1, 1, 1, None), (100, 9, None, 9),
+                                     (62, 45, None, 10), (60, 41, None, (12, 7))])
+def test_edge_shapes_match_oracle(dev, W, H, K, v):
+    im = synth.voronoi_lab(W, H, 3, 3.0, 11, K or 1)
+    vx, vy = (v if isinstance(v, tuple) else (v, v)) if v else (None, None)
+    g = O.make_grid(W, H, K=K, vx=vx, vy=vy)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=4)
+    out = run_gpu(im, dev, 4, K=K, v=v)
+    assert_theta_close(out["theta"], O.theta_to_rows(ref["theta"]), 1e-3, what=f"{W}x{H}")
+    Ro = oracle_slots(g, ref["cand"], ref["R"])
+    assert np.abs(out["R"] - Ro).max() <= 1e-4
+
+
+def test_far_outlier_pixel_uses_shifted_softmax(dev):
+    im = synth.voronoi_lab(64, 48, 4, 2.0, 12, 12)
+    lab = im.lab.clone()
+    lab[10, 10] = torch.tensor([900.0, -800.0, 700.0])   # ~100 std from every mean
+    im.lab = lab
+    g = O.make_grid(64, 48, K=12)
+    ref = O.run_em(lab.numpy(), g, max_iters=2)
+    out = run_gpu(im, dev, 2)
+    Ro = oracle_slots(g, ref["cand"], ref["R"])
+    assert np.isfinite(out["R"]).all()
+    assert np.abs(out["R"] - Ro).max() <= 1e-4
+    assert np.isfinite(out["hist"]).all()
+    assert out["ll_final"] == pytest.approx(ref["ll_final"], rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# full-size 4K image: sampled one-step parity in the launch shape of the bench
+# ---------------------------------------------------------------------------
+def test_4k_sampled_one_step(dev):
+    say("4K sampled one-step parity")
+    im = synth.config5_batch(device=dev, n_images=1)[0]
+    g = O.make_grid(im.W, im.H, K=im.K)
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    lab = im.lab.reshape(-1).contiguous()
+    m.init_seeds(lab)
+    m.em_iterate(lab, 3)
+    th3 = m.get_params()
+    R = m.export_responsibilities(lab).cpu().numpy()
+    m.em_iterate(lab, 1)
+    th4 = m.get_params()
+    lab_np = im.lab.cpu().numpy()
+    z = O.features(lab_np)
+    cand, _ = O.candidate_sets(g)
+    theta3 = O.rows_to_theta(th3)
+    rng = np.random.default_rng(5)
+    ks = rng.choice(g.K, 40, replace=False)
+    rows4 = np.empty((len(ks), 13))
+    want4 = np.empty((len(ks), 13))
+    for j, k in enumerate(ks):
+        xb, xe, yb, ye = O.window(g, int(k))
+        Rw, _, _ = O.estep(z[yb:ye, xb:xe], cand[yb:ye, xb:xe], theta3)
+        Rg = R.reshape(im.H, im.W, 9)[yb:ye, xb:xe]
+        # posterior parity on the window (slot layout)
+        sub = np.zeros((ye - yb, xe - xb, 9))
+        cw = cand[yb:ye, xb:xe]
+        cx = (np.arange(xb, xe) // g.vx)[None, :, None]
+        cy = (np.arange(yb, ye) // g.vy)[:, None, None]
+        s = 3 * (cw // g.nx - cy + 1) + (cw % g.nx - cx + 1)
+        yy, xx, jj = np.nonzero(cw >= 0)
+        sub[yy, xx, s[yy, xx, jj]] = Rw[yy, xx, jj]
+        assert np.abs(Rg - sub).max() <= 1e-5
+        pos = (cw == k).argmax(-1)
+        rk = np.take_along_axis(Rw, pos[..., None], -1).reshape(-1)
+        mu, sig, Nk = O.mstep_one(z[yb:ye, xb:xe].reshape(-1, 5), rk, theta3.mu[k],
+                                  theta3.sigma[k], O.Params())
+        want4[j] = O.theta_to_rows(O.Theta(mu[None], sig[None], np.array([Nk])))[0]
+        rows4[j] = th4[k]
+    e = assert_theta_close(rows4, want4, 1e-5, what="4K one step")
+    say("4K one-step errors", e)
