@@ -33,16 +33,17 @@ def _ptr(t: torch.Tensor) -> int:
 class GMMSP:
     """A batch of images (one image is a batch of one) bound to a workspace.
 
-    ``sizes``: sequence of (W, H); ``K`` (or ``v``): one value for all images or
-    one per image.  Inputs are packed float32 Lab tensors on the device (image b
+    ``sizes``: sequence of (W, H); ``K`` (or ``v``, an int or a (vx, vy) tuple):
+    one value for all images, or a list with one value per image.  Inputs are packed float32 Lab tensors on the device (image b
     at pixel offset ``pix_off[b]``)."""
 
     def __init__(self, sizes: Sequence[tuple], K=None, v=None, eps_s: float = 2.0,
                  eps_c: float = 8.0, lam: float = 8.0, n_min: float = 1e-3,
                  device="cuda"):
         n = len(sizes)
-        Ks = K if isinstance(K, (list, tuple)) else [K] * n
-        vs = v if isinstance(v, (list, tuple)) else [v] * n
+        # a list gives one value per image; a (vx, vy) tuple is one spacing for all
+        Ks = K if isinstance(K, list) else [K] * n
+        vs = v if isinstance(v, list) else [v] * n
         arr = (GmmspParams * n)()
         for b, (W, H) in enumerate(sizes):
             vb = vs[b]

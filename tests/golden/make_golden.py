@@ -36,9 +36,9 @@ def main():
     rng = np.random.default_rng(2024)
     pix = np.sort(rng.choice(im.W * im.H, N_SAMPLE, replace=False))
     Rs = O.to_slots(g, res["cand"], res["R"]).reshape(-1, 9)[pix]
-    # second-largest minus largest posterior, for the tie exclusion of the label check
+    # near ties (two largest posteriors within 2e-4) are excluded from the label check
     Rsort = np.sort(res["R"].reshape(-1, 9), axis=1)
-    margin = (Rsort[:, -1] - Rsort[:, -2]).astype(np.float32)
+    tie = (Rsort[:, -1] - Rsort[:, -2]) <= 2e-4
     np.savez_compressed(
         os.path.join(HERE, "cfg2_oracle.npz"),
         lab_sha256=np.array(lab_digest(lab)),
@@ -47,7 +47,8 @@ def main():
         ll_hist=np.array(res["ll_hist"]),
         ll_final=np.array(res["ll_final"]),
         labels=res["labels"].astype(np.int16),
-        margin=margin,
+        tie_bits=np.packbits(tie),
+        n_pix=np.array(tie.size),
         sample_pix=pix.astype(np.int64),
         sample_R=Rs,
     )
