@@ -135,6 +135,10 @@ struct gmmsp_handle {
   std::vector<int64_t> pairs;  // sum_i |K_i| per image
   DevPtrs P{};
   bool initialised = false;
+  // pipelined convergence checks: n_done snapshots in pinned host memory
+  static constexpr int kRing = 4;
+  int32_t* done_ring = nullptr;
+  hipEvent_t done_ev[kRing] = {};
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -143,6 +147,9 @@ struct gmmsp_handle {
   int64_t prof_pix = 0, prof_pairs = 0;
   ~gmmsp_handle() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : done_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (done_ring) (void)hipHostFree(done_ring);
   }
 };
 
@@ -233,6 +240,9 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   if (e == hipSuccess) e = launch_clear_records(P, s);
   if (e == hipSuccess) e = launch_reset_state(P, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->done_ring, sizeof(int32_t) * gmmsp_handle::kRing);
+  for (int i = 0; i < gmmsp_handle::kRing && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&h->done_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     delete h;
     return hip_fail(e, "gmmsp_create");
@@ -343,11 +353,18 @@ int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, d
     if (e != hipSuccess) return hip_fail(e, "em pass");
     ++launched;
     if (rel_tol > 0.0) {
-      int32_t n_done = 0;
-      e = hipMemcpyAsync(&n_done, h->P.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      // snapshot the stopped-image count after pass it; wait for the snapshot
+      // of pass it-1 while pass it is already queued, so the GPU never idles
+      const int slot = it % gmmsp_handle::kRing;
+      e = hipMemcpyAsync(&h->done_ring[slot], h->P.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(h->done_ev[slot], s);
+      if (e == hipSuccess && it >= 1) {
+        const int prev = (it - 1) % gmmsp_handle::kRing;
+        e = hipEventSynchronize(h->done_ev[prev]);
+        // every image had stopped after pass it-1; the queued pass it skips them all
+        if (e == hipSuccess && h->done_ring[prev] >= h->n_img) break;
+      }
       if (e != hipSuccess) return hip_fail(e, "em convergence check");
-      if (n_done >= h->n_img) break;
     }
   }
   if (h->profile) {

@@ -211,29 +211,211 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
   return l;
 }
 
-// One step of the butterfly reduce-scatter: N values in, ceil(N/2) out.  Lanes
-// with (lane & MASK) == 0 keep the even entries summed with their partner's,
-// the others the odd ones; after the six steps lane l holds the wave totals of
-// entries bitrev6(l) and 64 + bitrev6(l).
+// Butterfly reduce-scatter of per-lane sums across a 64-lane wave.  Each step
+// halves the number of values: in a pair of partner lanes the one whose keep
+// bit is 0 keeps the even entries summed with its partner's, the other the odd
+// ones.  Keep bits go 5, 4, 3, 2, 1, 0, so after the six steps lane l holds the
+// wave totals of entries bitrev6(l) and 64 + bitrev6(l).
+#ifndef GMMSP_REDUCE_DPP
+#define GMMSP_REDUCE_DPP 1
+#endif
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// partner = lane ^ MASK through ds_bpermute
 template <int N, int MASK, int CAP>
-__device__ __forceinline__ void bfly(float (&v)[CAP], int lane) {
+__device__ __forceinline__ void bfly_shfl(float (&v)[CAP], int lane) {
+  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
   const bool hi = (lane & MASK) != 0;
   if (N & 1) v[N] = 0.f;  // odd count: the pair partner of the last entry is zero
 #pragma unroll
   for (int i = 0; i < (N + 1) / 2; ++i) {
-    static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-    const float a = v[2 * i];
-    const float b = v[2 * i + 1];
+    const float a = v[2 * i], b = v[2 * i + 1];
     const float send = hi ? a : b;
     const float keep = hi ? b : a;
     v[i] = keep + __shfl_xor(send, MASK, 64);
   }
 }
 
+// keep bit 5 (lanes 0-31 keep even entries): v_permlane32_swap exchanges the
+// upper half of the first operand with the lower half of the second.
+template <int N, int CAP>
+__device__ __forceinline__ void bfly_swap32(float (&v)[CAP]) {
+  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
+  if (N & 1) v[N] = 0.f;
+#pragma unroll
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]),
+                                                    __float_as_uint(v[2 * i + 1]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+// keep bit 4: v_permlane16_swap exchanges odd 16-lane rows of the first operand
+// with even rows of the second.
+template <int N, int CAP>
+__device__ __forceinline__ void bfly_swap16(float (&v)[CAP]) {
+  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
+  if (N & 1) v[N] = 0.f;
+#pragma unroll
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[2 * i]),
+                                                    __float_as_uint(v[2 * i + 1]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+// keep bit BIT, partner given by the DPP control CTRL (an involution inside a
+// 16-lane row that flips BIT and keeps the higher bits)
+template <int N, int BIT, int CTRL, int CAP>
+__device__ __forceinline__ void bfly_dpp(float (&v)[CAP], int lane) {
+  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
+  const bool hi = ((lane >> BIT) & 1) != 0;
+  if (N & 1) v[N] = 0.f;
+#pragma unroll
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    const float a = v[2 * i], b = v[2 * i + 1];
+    const float send = hi ? a : b;
+    const float keep = hi ? b : a;
+    v[i] = keep + dpp<CTRL>(send);
+  }
+}
+
+template <int CAP>
+__device__ __forceinline__ void wave_reduce_scatter_117(float (&v)[CAP], int lane) {
+#if GMMSP_REDUCE_DPP
+  bfly_swap32<117>(v);
+  bfly_swap16<59>(v);
+  bfly_dpp<30, 3, 0x128>(v, lane);  // row_ror:8, partner lane ^ 8
+  bfly_dpp<15, 2, 0x141>(v, lane);  // row_half_mirror, partner lane ^ 7
+  bfly_dpp<8, 1, 0x4E>(v, lane);    // quad_perm [2,3,0,1], partner lane ^ 2
+  bfly_dpp<4, 0, 0xB1>(v, lane);    // quad_perm [1,0,3,2], partner lane ^ 1
+#else
+  bfly_shfl<117, 32>(v, lane);
+  bfly_shfl<59, 16>(v, lane);
+  bfly_shfl<30, 8>(v, lane);
+  bfly_shfl<15, 4>(v, lane);
+  bfly_shfl<8, 2>(v, lane);
+  bfly_shfl<4, 1>(v, lane);
+#endif
+}
+
+#ifndef GMMSP_WAVES_PER_EU
+#define GMMSP_WAVES_PER_EU 0
+#endif
+#if GMMSP_WAVES_PER_EU > 0
+#define CELLS_ATTR __attribute__((amdgpu_waves_per_eu(GMMSP_WAVES_PER_EU)))
+#else
+#define CELLS_ATTR
+#endif
+
+// E-step of NP pixels per lane against the nine records of the wave's cell:
+// e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
+// shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
+// Each record value is read once (scalar load) for all NP pixels.
+template <int NP>
+__device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (&xr)[NP],
+                                             const float (&yr)[NP], const float (&L)[NP],
+                                             const float (&A)[NP], const float (&B)[NP],
+                                             float (&e)[NP][kSlots], float (&sum)[NP],
+                                             float (&shift)[NP]) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) sum[p] = 0.f;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      e[p][s] = __builtin_amdgcn_exp2f(eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]));
+      sum[p] += e[p][s];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    shift[p] = 0.f;
+    if (sum[p] < 0x1p-100f) {
+      // every candidate is far away: subtract the largest exponent first
+      float lv[kSlots];
+      float m = -INFINITY;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        lv[s] = eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]);
+        m = fmaxf(m, lv[s]);
+      }
+      float t = 0.f;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        e[p][s] = __builtin_amdgcn_exp2f(lv[s] - m);
+        t += e[p][s];
+      }
+      sum[p] = t;
+      shift[p] = m;
+    }
+  }
+}
+
+// M-step sufficient statistics of NP pixels (weights inv[p] = 1 / sum[p], or 0
+// for a masked pixel) added to the 9 x 13 per-lane accumulators.
+template <int NP>
+__device__ __forceinline__ void accumulate_stats(const AS4 float* rec, float* acc,
+                                                 const float (&e)[NP][kSlots],
+                                                 const float (&inv)[NP], const float (&xr)[NP],
+                                                 const float (&yr)[NP], const float (&L)[NP],
+                                                 const float (&A)[NP], const float (&B)[NP]) {
+  float xx[NP], xy[NP], yy[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    xx[p] = xr[p] * xr[p];
+    xy[p] = xr[p] * yr[p];
+    yy[p] = yr[p] * yr[p];
+  }
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const AS4 float* f = rec + s * kRecFloats;
+    const float mL = f[R_ML], ma = f[R_MA], mb = f[R_MB];
+    float* a = acc + s * kStats;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const float R = e[p][s] * inv[p];
+      a[S_N] += R;
+      a[S_X] = fmaf(R, xr[p], a[S_X]);
+      a[S_Y] = fmaf(R, yr[p], a[S_Y]);
+      a[S_XX] = fmaf(R, xx[p], a[S_XX]);
+      a[S_XY] = fmaf(R, xy[p], a[S_XY]);
+      a[S_YY] = fmaf(R, yy[p], a[S_YY]);
+      const float dL = L[p] - mL;
+      const float da = A[p] - ma;
+      const float db = B[p] - mb;
+      const float rL = R * dL;
+      a[S_L] += rL;
+      a[S_LL] = fmaf(rL, dL, a[S_LL]);
+      const float ra = R * da;
+      a[S_A] += ra;
+      a[S_AA] = fmaf(ra, da, a[S_AA]);
+      a[S_AB] = fmaf(ra, db, a[S_AB]);
+      const float rb = R * db;
+      a[S_B] += rb;
+      a[S_BB] = fmaf(rb, db, a[S_BB]);
+    }
+  }
+}
+
+// advance a lane's (row, col) inside a cell of width w by the step (dr, dc)
+__device__ __forceinline__ void advance(int& row, int& col, int dr, int dc, int w) {
+  col += dc;
+  row += dr;
+  if (col >= w) {
+    col -= w;
+    row += 1;
+  }
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_cells(DevPtrs P, const float* __restrict__ lab,
-                                               int32_t* __restrict__ out_i,
-                                               float* __restrict__ out_f) {
+__global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float* __restrict__ lab,
+                                                          int32_t* __restrict__ out_i,
+                                                          float* __restrict__ out_f) {
   const int lane = threadIdx.x & 63;
   const int cell = __builtin_amdgcn_readfirstlane(
       (int)(blockIdx.x * kCellsPerBlock + (threadIdx.x >> 6)));
@@ -248,7 +430,8 @@ __global__ __launch_bounds__(256) void k_cells(DevPtrs P, const float* __restric
   const int npix = w * h;
   const int64_t pix0 = Ip->pix_off + (int64_t)y0 * W + x0;
   const float* img = lab + 3 * pix0;
-  const AS4 float* rec = cptr(P.rec) + (size_t)cell * (kSlots * kRecFloats);
+  const AS4 float* rec0 = cptr(P.rec) + (size_t)cell * (kSlots * kRecFloats);
+  const AS4 float* rec = rec0;
 
   if (MODE == M_EXPORT_CAND) {
     const int nx = Ip->nx, ny = Ip->ny;
@@ -266,101 +449,92 @@ __global__ __launch_bounds__(256) void k_cells(DevPtrs P, const float* __restric
     return;
   }
 
-  // 117 statistics plus one zero pad, so every butterfly step reads pairs
-  float acc[kSlots * kStats + 1];
-  if (MODE == M_STATS) {
-#pragma unroll
-    for (int i = 0; i < kSlots * kStats + 1; ++i) acc[i] = 0.f;
-  }
   float llacc = 0.f;
 
-  // lane -> (row, col) inside the cell, advanced by 64 pixels per iteration
-  int row = lane / w, col = lane - (lane / w) * w;
-  const int drow = 64 / w, dcol = 64 - (64 / w) * w;
-
-  for (int p = lane; p < npix; p += 64) {
-    const float* px = img + 3 * (row * W + col);
-    const float L = px[0], A = px[1], B = px[2];
-    const float xr = (float)col, yr = (float)row;
-
-    float e[kSlots];
-    float sum = 0.f;
+  if (MODE == M_STATS) {
+    // 117 statistics plus one zero pad, so every butterfly step reads pairs
+    float acc[kSlots * kStats + 1];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      e[s] = __builtin_amdgcn_exp2f(eval_l(rec + s * kRecFloats, xr, yr, L, A, B));
-      sum += e[s];
+    for (int i = 0; i < kSlots * kStats + 1; ++i) acc[i] = 0.f;
+    // Rounds of 128 pixels: lane l takes pixels 128 r + l and 128 r + 64 + l.
+    // Rounds that hold more than 64 pixels run as pairs (the second pixel of a
+    // lane masked past the end); a last round of at most 64 pixels runs after
+    // the loop, one pixel per lane, so the loop body has a single path and the
+    // accumulators stay in place.
+    int r1 = lane / w, c1 = lane - r1 * w;
+    int r2 = (lane + 64) / w, c2 = (lane + 64) - r2 * w;
+    const int dr = 128 / w, dc = 128 - (128 / w) * w;
+    const int n_pair = npix > 64 ? (npix - 64 + 127) >> 7 : 0;  // rounds with base + 64 < npix
+    for (int rd = 0; rd < n_pair; ++rd) {
+      const int base = rd << 7;
+      // The 144 record floats do not fit the scalar registers; an opaque zero
+      // offset keeps the compiler from hoisting them out of the loop, so each
+      // round re-reads them with scalar loads instead of spilling them to
+      // vector-register lanes.
+      int zero = 0;
+      asm volatile("" : "+s"(zero));
+      const AS4 float* rec = rec0 + zero;
+      const bool v2 = base + 64 + lane < npix;
+      const float* q1 = img + 3 * (r1 * W + c1);
+      const float* q2 = img + (v2 ? 3 * (r2 * W + c2) : 3 * (r1 * W + c1));
+      const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
+      const float xr[2] = {(float)c1, (float)c2}, yr[2] = {(float)r1, (float)r2};
+      float e[2][kSlots], sum[2], shift[2];
+      estep_pixels<2>(rec, xr, yr, L, A, B, e, sum, shift);
+      const float inv[2] = {__builtin_amdgcn_rcpf(sum[0]), v2 ? __builtin_amdgcn_rcpf(sum[1]) : 0.f};
+      llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
+      llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;
+      accumulate_stats<2>(rec, acc, e, inv, xr, yr, L, A, B);
+      advance(r1, c1, dr, dc, w);
+      advance(r2, c2, dr, dc, w);
     }
-    float shift = 0.f;
-    if (sum < 0x1p-100f) {
-      // every candidate is far away: subtract the largest exponent first
-      float lv[kSlots];
-      float m = -INFINITY;
-#pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        lv[s] = eval_l(rec + s * kRecFloats, xr, yr, L, A, B);
-        m = fmaxf(m, lv[s]);
-      }
-      sum = 0.f;
-#pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        e[s] = __builtin_amdgcn_exp2f(lv[s] - m);
-        sum += e[s];
-      }
-      shift = m;
+    if ((n_pair << 7) + lane < npix) {
+      const float* q1 = img + 3 * (r1 * W + c1);
+      const float xr[1] = {(float)c1}, yr[1] = {(float)r1};
+      const float L[1] = {q1[0]}, A[1] = {q1[1]}, B[1] = {q1[2]};
+      float e[1][kSlots], sum[1], shift[1];
+      estep_pixels<1>(rec, xr, yr, L, A, B, e, sum, shift);
+      const float inv[1] = {__builtin_amdgcn_rcpf(sum[0])};
+      llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
+      accumulate_stats<1>(rec, acc, e, inv, xr, yr, L, A, B);
     }
-    const float inv = __builtin_amdgcn_rcpf(sum);
-    llacc += __builtin_amdgcn_logf(sum) + shift;
-
-    if (MODE == M_STATS) {
-      const float xx = xr * xr, xy = xr * yr, yy = yr * yr;
+    wave_reduce_scatter_117(acc, lane);
+    const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
+    double* part = P.part + (size_t)cell * kPartStride;
+    part[r] = (double)acc[0];
+    if (64 + r < kSlots * kStats) part[64 + r] = (double)acc[1];
+  } else {
+    // one pixel per lane per step of 64
+    int row = lane / w, col = lane - (lane / w) * w;
+    const int drow = 64 / w, dcol = 64 - (64 / w) * w;
+    for (int p = lane; p < npix; p += 64) {
+      const float* px = img + 3 * (row * W + col);
+      const float xr[1] = {(float)col}, yr[1] = {(float)row};
+      const float L[1] = {px[0]}, A[1] = {px[1]}, B[1] = {px[2]};
+      float e[1][kSlots], sum[1], shift[1];
+      estep_pixels<1>(rec, xr, yr, L, A, B, e, sum, shift);
+      const float inv = __builtin_amdgcn_rcpf(sum[0]);
+      llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
+      if (MODE == M_LABEL) {
+        // Eq. obtLi: the largest posterior, ties to the smallest k (slots
+        // ascend in k and the comparison is strict)
+        int best = 0;
+        float be = e[0][0];
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        const AS4 float* f = rec + s * kRecFloats;
-        float* a = acc + s * kStats;
-        const float R = e[s] * inv;
-        a[S_N] += R;
-        a[S_X] = fmaf(R, xr, a[S_X]);
-        a[S_Y] = fmaf(R, yr, a[S_Y]);
-        a[S_XX] = fmaf(R, xx, a[S_XX]);
-        a[S_XY] = fmaf(R, xy, a[S_XY]);
-        a[S_YY] = fmaf(R, yy, a[S_YY]);
-        const float dL = L - f[R_ML];
-        const float da = A - f[R_MA];
-        const float db = B - f[R_MB];
-        const float rL = R * dL;
-        a[S_L] += rL;
-        a[S_LL] = fmaf(rL, dL, a[S_LL]);
-        const float ra = R * da;
-        a[S_A] += ra;
-        a[S_AA] = fmaf(ra, da, a[S_AA]);
-        a[S_AB] = fmaf(ra, db, a[S_AB]);
-        const float rb = R * db;
-        a[S_B] += rb;
-        a[S_BB] = fmaf(rb, db, a[S_BB]);
-      }
-    } else if (MODE == M_LABEL) {
-      int best = 0;
-      float be = e[0];
-#pragma unroll
-      for (int s = 1; s < kSlots; ++s) {
-        if (e[s] > be) {
-          be = e[s];
-          best = s;
+        for (int s = 1; s < kSlots; ++s) {
+          if (e[0][s] > be) {
+            be = e[0][s];
+            best = s;
+          }
         }
-      }
-      const int kx = ccx + (best % 3) - 1, ky = ccy + (best / 3) - 1;
-      out_i[pix0 + (int64_t)row * W + col] = ky * Ip->nx + kx;
-    } else if (MODE == M_EXPORT_R) {
-      float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
+        const int kx = ccx + (best % 3) - 1, ky = ccy + (best / 3) - 1;
+        out_i[pix0 + (int64_t)row * W + col] = ky * Ip->nx + kx;
+      } else if (MODE == M_EXPORT_R) {
+        float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) dst[s] = e[s] * inv;
-    }
-
-    col += dcol;
-    row += drow;
-    if (col >= w) {
-      col -= w;
-      row += 1;
+        for (int s = 0; s < kSlots; ++s) dst[s] = e[0][s] * inv;
+      }
+      advance(row, col, drow, dcol, w);
     }
   }
 
@@ -369,20 +543,7 @@ __global__ __launch_bounds__(256) void k_cells(DevPtrs P, const float* __restric
     double ll = (double)llacc;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
-    double* part = P.part + (size_t)cell * kPartStride;
-    if (lane == 0) part[kLLSlot] = kLn2 * ll + (double)npix * Ip->lncmax;
-  }
-  if (MODE == M_STATS) {
-    bfly<117, 32>(acc, lane);
-    bfly<59, 16>(acc, lane);
-    bfly<30, 8>(acc, lane);
-    bfly<15, 4>(acc, lane);
-    bfly<8, 2>(acc, lane);
-    bfly<4, 1>(acc, lane);
-    const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
-    double* part = P.part + (size_t)cell * kPartStride;
-    part[r] = (double)acc[0];
-    if (64 + r < kSlots * kStats) part[64 + r] = (double)acc[1];
+    if (lane == 0) P.part[(size_t)cell * kPartStride + kLLSlot] = kLn2 * ll + (double)npix * Ip->lncmax;
   }
 }
 
