@@ -1,0 +1,84 @@
+"""Pins of the warm-start network oracle: convolution against scipy, backward
+against central finite differences, bfloat16 rounding against torch, and the
+exact inverse relation between targets and theta^0."""
+import numpy as np
+import pytest
+import torch
+from scipy.signal import correlate2d
+
+from oracle import ws_oracle as WS
+
+
+def test_param_count():
+    # 8*9*32+32 + 2*(32*9*32+32) + 32*9*10+10
+    assert WS.param_count() == 2336 + 2 * 9248 + 2890
+
+
+def test_conv3x3_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(6, 7, 3))
+    W = rng.normal(size=(4, 9, 3))
+    b = rng.normal(size=4)
+    got = WS.conv3x3(x, W, b)
+    for o in range(4):
+        want = b[o] + sum(correlate2d(x[:, :, i], W[o, :, i].reshape(3, 3), mode="same")
+                          for i in range(3))
+        np.testing.assert_allclose(got[:, :, o], want, rtol=1e-12, atol=1e-12)
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    ny, nx = 4, 5
+    params = rng.normal(scale=0.3, size=WS.param_count())
+    x0 = rng.normal(size=(ny, nx, WS.C_IN))
+    tgt = rng.normal(size=(ny, nx, WS.C_OUT))
+    loss, g = WS.loss_and_grads(params, x0, tgt, ny * nx)
+    idx = rng.choice(params.size, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += h
+        p2[i] -= h
+        l1, _ = WS.loss_and_grads(p1, x0, tgt, ny * nx)
+        l2, _ = WS.loss_and_grads(p2, x0, tgt, ny * nx)
+        fd = (l1 - l2) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.normal(size=5000).astype(np.float32) * 10.0 ** rng.integers(-6, 6, 5000),
+                        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0], np.float32)])
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(WS.bf16_round(x), want)
+
+
+def test_features_of_constant_cells_and_border_channel():
+    lab = np.zeros((12, 20, 3), np.float32)
+    lab[..., 0], lab[..., 1], lab[..., 2] = 70.0, -32.0, 16.0
+    f = WS.features(lab, 4, 4, 5, 3)
+    np.testing.assert_allclose(f[..., 0], 0.4)
+    np.testing.assert_allclose(f[..., 1], -0.5)
+    np.testing.assert_allclose(f[..., 2], 0.25)
+    np.testing.assert_allclose(f[..., 3:6], 0.0, atol=1e-12)
+    # distance to the border in cells, capped at 3, over 3: a 5 x 3 grid
+    np.testing.assert_allclose(f[..., 6] * 3, [[0, 0, 0, 0, 0], [0, 1, 1, 1, 0], [0, 0, 0, 0, 0]])
+
+
+def test_zero_output_is_grid_init_with_cell_mean_colour():
+    rng = np.random.default_rng(3)
+    lab = rng.uniform(0, 50, (19 * 2, 19 * 3, 3)).astype(np.float32)
+    f = WS.features(lab, 19, 19, 3, 2)
+    rows = WS.theta0_rows(np.zeros((2, 3, 10)), f, 19, 19, 8.0)
+    assert rows[4, 0] == 19 + 9 and rows[4, 1] == 19 + 9          # k = (1, 1)
+    np.testing.assert_allclose(rows[4, 2:5], lab[19:38, 19:38].reshape(-1, 3).mean(0), rtol=1e-6)
+    np.testing.assert_allclose(rows[:, [5, 7, 8, 9, 11]], [[361, 361, 64, 64, 64]] * 6)
+    assert np.all(rows[:, [6, 10]] == 0)
+
+
+def test_targets_invert_theta0():
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(3, 4, 8)) * 0.5
+    out = rng.uniform(-2, 2, (3, 4, 10))
+    rows = WS.theta0_rows(out, f, 17, 15, 8.0)
+    np.testing.assert_allclose(WS.targets(rows, f, 17, 15, 8.0), out, rtol=1e-10, atol=1e-12)
