@@ -162,6 +162,81 @@ int gmmsp_profile_enable(gmmsp_handle* h, int32_t enable);
 int gmmsp_profile_read(gmmsp_handle* h, double* estep_ms, int32_t* launches,
                        int64_t* pixel_evals, int64_t* pair_evals, int32_t reset);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper): a conv3x3 network on the seed
+ * grid, BF16 weights and activations with FP32 accumulation on the matrix
+ * cores, predicts theta^0 in place of the grid initialisation of Sec. III-C;
+ * the EM above then runs unchanged.  Layers: 16 -> 32 -> 32 -> 32 -> 10, ReLU
+ * between them, zero padding at the grid border.
+ *   inputs (16 per superpixel, over its own v_x x v_y seed cell, s its seed
+ *   pixel, h = floor(v / 2)): (mean_L - 50)/50, mean_a/64, mean_b/64,
+ *     std_L/16, std_a/16, std_b/16, min(k_x, k_y, n_x-1-k_x, n_y-1-k_y, 3)/3,
+ *     (colour(s) - mean)/16 (3), (mean of the last h columns - mean of the
+ *     first h)/32 (3), the same for rows (3)
+ *   outputs o[0..9] -> theta^0: mu_x = s_x + v_x o0, mu_y = s_y + v_y o1,
+ *     mu_c = colour(s) + lambda o_{2..4}, Sigma = diag(v_x^2 e^{2 o5},
+ *     v_y^2 e^{2 o6}, lambda^2 e^{2 o7..9}) (log-scales clipped to [-4, 4]),
+ *     then the eigenvalue floors; outputs outside the caller's mask count as
+ *     0, so the all-zero output is the grid initialisation exactly, and a
+ *     superpixel with a non-finite output gets the grid initialisation.
+ * Parameters: one flat FP32 vector (caller-owned device memory), per layer
+ * W[cout][9][cin] (tap t = 3 (dy + 1) + (dx + 1)) then b[cout].
+ * ------------------------------------------------------------------------ */
+#define GMMSP_WS_NPARAM 26026
+
+/* Buffers of the warm-start workspace that gmmsp_ws_read / gmmsp_ws_write reach. */
+typedef enum gmmsp_ws_buffer {
+  GMMSP_WS_FEAT = 0,   /* float32 [n_sp][16] inputs                        */
+  GMMSP_WS_X0 = 1,     /* bf16 [n_sp][16] inputs as the first layer reads   */
+  GMMSP_WS_Y1 = 2,     /* bf16 [n_sp][32] activation after layer 1 (ReLU)   */
+  GMMSP_WS_Y2 = 3,
+  GMMSP_WS_Y3 = 4,
+  GMMSP_WS_OUT = 5,    /* float32 [n_sp][16] outputs (10 used)              */
+  GMMSP_WS_TGT = 6,    /* float32 [n_sp][16] training targets (10 used)     */
+  GMMSP_WS_G4 = 7,     /* bf16 [n_sp][16] gradient at the outputs, 2 (o - t) / 10 */
+  GMMSP_WS_G3 = 8,     /* bf16 [n_sp][32] gradient at layer-3 output, ReLU applied */
+  GMMSP_WS_G2 = 9,
+  GMMSP_WS_G1 = 10,
+  GMMSP_WS_GRAD = 11   /* float32 [GMMSP_WS_NPARAM] gradient of the last step */
+} gmmsp_ws_buffer;
+
+/* Device workspace of the warm start for this handle's batch, and attaching it
+ * (builds the seed-grid neighbour table on `stream`, then synchronises it). */
+int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes);
+int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream);
+
+/* Network inputs of every superpixel of the batch from the Lab images. */
+int gmmsp_ws_features(gmmsp_handle* h, const float* lab_dev, void* stream);
+
+/* Forward pass over the superpixels of images [b0, b1) with parameters
+ * params_dev (GMMSP_WS_NPARAM floats). */
+int gmmsp_ws_forward(gmmsp_handle* h, const float* params_dev, int32_t b0, int32_t b1,
+                     void* stream);
+
+/* theta^0 of every image from the last forward outputs (see above; bit c of
+ * output_mask selects output c), with the eigenvalue floors, and reset of the
+ * iteration state: the handle is then initialised as by gmmsp_init_seeds. */
+int gmmsp_ws_apply(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask, void* stream);
+
+/* Training targets from the handle's current theta (for instance plain EM
+ * after some passes): the inverse of the map above. */
+int gmmsp_ws_targets(gmmsp_handle* h, const float* lab_dev, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with
+ * step >= 1) on the mean squared error over images [b0, b1): forward, loss,
+ * backward (input and weight gradients on the matrix cores, fixed-order
+ * reductions) and the update of params_dev, m_dev, v_dev (caller-owned,
+ * GMMSP_WS_NPARAM floats each).  loss_host (nullable): the loss before the
+ * update; when given, `stream` is synchronised. */
+int gmmsp_ws_train_step(gmmsp_handle* h, float* params_dev, float* m_dev, float* v_dev,
+                        int32_t step, float lr, int32_t b0, int32_t b1, double* loss_host,
+                        void* stream);
+
+/* Copy a workspace buffer to or from the host (synchronises `stream`); bytes
+ * must not exceed the buffer's size. */
+int gmmsp_ws_read(gmmsp_handle* h, int32_t which, void* host, size_t bytes, void* stream);
+int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t bytes, void* stream);
+
 const char* gmmsp_last_error(void);
 
 #ifdef __cplusplus

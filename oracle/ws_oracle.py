@@ -12,23 +12,29 @@ Definitions used by both the oracle and the kernels:
 
 * positions: the n_x x n_y seed grid of each image, superpixel order
   k = k_y n_x + k_x;
-* features (8 channels, the last one zero) of seed cell k, over the pixels
-  [k_x v_x, (k_x+1) v_x) x [k_y v_y, (k_y+1) v_y):
-  (mean_L - 50) / 50, mean_a / 64, mean_b / 64, std_L / 16, std_a / 16,
-  std_b / 16 (population standard deviations), min(k_x, k_y, n_x-1-k_x,
-  n_y-1-k_y, 3) / 3, 0;
-* network: conv3x3 8->32, ReLU, 32->32, ReLU, 32->32, ReLU, 32->10, zero
+* features (16 channels) of seed cell k, over the pixels
+  [k_x v_x, (k_x+1) v_x) x [k_y v_y, (k_y+1) v_y), with s the seed pixel of
+  Sec. III-C and h = floor(v / 2):
+  0-2  (mean_L - 50) / 50, mean_a / 64, mean_b / 64,
+  3-5  std_L / 16, std_a / 16, std_b / 16 (population standard deviations),
+  6    min(k_x, k_y, n_x-1-k_x, n_y-1-k_y, 3) / 3,
+  7-9  (colour(s) - mean) / 16,
+  10-12 (mean over columns >= v_x - h  -  mean over columns < h) / 32,
+  13-15 (mean over rows >= v_y - h  -  mean over rows < h) / 32
+  (channels 10-15 are 0 when h = 0);
+* network: conv3x3 16->32, ReLU, 32->32, ReLU, 32->32, ReLU, 32->10, zero
   padding at the grid border, out[y][x][o] = b[o] + sum_{t, i} W[o][t][i]
   in[y+dy_t][x+dx_t][i] with tap t = 3 (dy + 1) + (dx + 1);  weights and
   activations rounded to bfloat16 (round to nearest, ties to even), sums
   exact here (FP32 on the GPU);
-* outputs o[0..9] -> theta^0: mu_x = s_x + v_x o0, mu_y = s_y + v_y o1 (s the
-  seed pixel of Sec. III-C), mu_c = mean_c + lambda o_{2..4},
-  Sigma = diag(v_x^2 e^{2 o5}, v_y^2 e^{2 o6}, lambda^2 e^{2 o7},
-  lambda^2 e^{2 o8}, lambda^2 e^{2 o9}) with every o5..o9 clipped to [-4, 4],
-  followed by the eigenvalue floors of Eqs. mlams, mlamc;
-* targets from converged parameters theta*: the inverse map, each log-scale
-  clipped to [-4, 4];
+* outputs o[0..9] -> theta^0 (an output whose bit is clear in the mask counts
+  as 0): mu_x = s_x + v_x o0, mu_y = s_y + v_y o1, mu_c = colour(s) +
+  lambda o_{2..4}, Sigma = diag(v_x^2 e^{2 o5}, v_y^2 e^{2 o6},
+  lambda^2 e^{2 o7}, lambda^2 e^{2 o8}, lambda^2 e^{2 o9}) with every o5..o9
+  clipped to [-4, 4], followed by the eigenvalue floors of Eqs. mlams, mlamc;
+  a zero output is the grid initialisation of Sec. III-C exactly;
+* targets from parameters theta* (of plain EM after some passes): the inverse
+  map, each log-scale clipped to [-4, 4];
 * loss: mean over positions and the 10 channels of (o - target)^2.
 """
 from __future__ import annotations
@@ -37,7 +43,7 @@ import math
 
 import numpy as np
 
-C_IN, C_HID, C_OUT = 8, 32, 10
+C_IN, C_HID, C_OUT = 16, 32, 10
 LAYERS = [(C_IN, C_HID), (C_HID, C_HID), (C_HID, C_HID), (C_HID, C_OUT)]
 LOG_CLIP = 4.0
 
@@ -153,14 +159,24 @@ def loss_and_grads(params: np.ndarray, x0: np.ndarray, target: np.ndarray, count
 def features(lab: np.ndarray, vx: int, vy: int, nx: int, ny: int) -> np.ndarray:
     lab = np.asarray(lab, dtype=np.float64)
     f = np.zeros((ny, nx, C_IN))
+    hx, hy = vx // 2, vy // 2
     for ky in range(ny):
         for kx in range(nx):
-            px = lab[ky * vy:(ky + 1) * vy, kx * vx:(kx + 1) * vx].reshape(-1, 3)
+            cell = lab[ky * vy:(ky + 1) * vy, kx * vx:(kx + 1) * vx]
+            px = cell.reshape(-1, 3)
             m = px.mean(axis=0)
             s = px.std(axis=0)
+            sx, sy = seed_xy(vx, vy, kx, ky)
             f[ky, kx, 0:3] = [(m[0] - 50.0) / 50.0, m[1] / 64.0, m[2] / 64.0]
             f[ky, kx, 3:6] = s / 16.0
             f[ky, kx, 6] = min(kx, ky, nx - 1 - kx, ny - 1 - ky, 3) / 3.0
+            f[ky, kx, 7:10] = (lab[sy, sx] - m) / 16.0
+            if hx > 0:
+                f[ky, kx, 10:13] = (cell[:, vx - hx:].reshape(-1, 3).mean(0)
+                                    - cell[:, :hx].reshape(-1, 3).mean(0)) / 32.0
+            if hy > 0:
+                f[ky, kx, 13:16] = (cell[vy - hy:].reshape(-1, 3).mean(0)
+                                    - cell[:hy].reshape(-1, 3).mean(0)) / 32.0
     return f
 
 
@@ -168,20 +184,24 @@ def seed_xy(vx, vy, kx, ky):
     return kx * vx + vx // 2, ky * vy + vy // 2
 
 
-def theta0_rows(out: np.ndarray, feat: np.ndarray, vx: int, vy: int, lam: float) -> np.ndarray:
+ALL_OUTPUTS = (1 << C_OUT) - 1
+
+
+def theta0_rows(out: np.ndarray, lab: np.ndarray, vx: int, vy: int, lam: float,
+                mask: int = ALL_OUTPUTS) -> np.ndarray:
     """Rows (mu_x mu_y mu_L mu_a mu_b S_xx S_xy S_yy S_LL S_aa S_ab S_bb N) from
     network outputs (before the eigenvalue floors, which set_params applies)."""
     ny, nx, _ = out.shape
+    lab = np.asarray(lab, dtype=np.float64)
+    use = np.array([(mask >> c) & 1 for c in range(C_OUT)], dtype=np.float64)
     rows = np.zeros((ny * nx, 13))
     for ky in range(ny):
         for kx in range(nx):
-            o = out[ky, kx].astype(np.float64)
+            o = out[ky, kx].astype(np.float64) * use
             sx, sy = seed_xy(vx, vy, kx, ky)
-            f = feat[ky, kx]
-            mean = np.array([50.0 + 50.0 * f[0], 64.0 * f[1], 64.0 * f[2]])
             ls = np.clip(o[5:10], -LOG_CLIP, LOG_CLIP)
             k = ky * nx + kx
-            rows[k, 0:5] = [sx + vx * o[0], sy + vy * o[1], *(mean + lam * o[2:5])]
+            rows[k, 0:5] = [sx + vx * o[0], sy + vy * o[1], *(lab[sy, sx] + lam * o[2:5])]
             rows[k, 5] = vx * vx * math.exp(2 * ls[0])
             rows[k, 7] = vy * vy * math.exp(2 * ls[1])
             rows[k, 8] = lam * lam * math.exp(2 * ls[2])
@@ -190,18 +210,18 @@ def theta0_rows(out: np.ndarray, feat: np.ndarray, vx: int, vy: int, lam: float)
     return rows
 
 
-def targets(rows: np.ndarray, feat: np.ndarray, vx: int, vy: int, lam: float) -> np.ndarray:
-    ny, nx, _ = feat.shape
+def targets(rows: np.ndarray, lab: np.ndarray, vx: int, vy: int, nx: int, ny: int,
+            lam: float) -> np.ndarray:
+    rows = np.asarray(rows, dtype=np.float64)
+    lab = np.asarray(lab, dtype=np.float64)
     t = np.zeros((ny, nx, C_OUT))
     for ky in range(ny):
         for kx in range(nx):
             r = rows[ky * nx + kx]
             sx, sy = seed_xy(vx, vy, kx, ky)
-            f = feat[ky, kx]
-            mean = np.array([50.0 + 50.0 * f[0], 64.0 * f[1], 64.0 * f[2]])
             t[ky, kx, 0] = (r[0] - sx) / vx
             t[ky, kx, 1] = (r[1] - sy) / vy
-            t[ky, kx, 2:5] = (r[2:5] - mean) / lam
+            t[ky, kx, 2:5] = (r[2:5] - lab[sy, sx]) / lam
             var = [r[5] / (vx * vx), r[7] / (vy * vy), r[8] / lam ** 2, r[9] / lam ** 2,
                    r[11] / lam ** 2]
             t[ky, kx, 5:10] = np.clip(0.5 * np.log(var), -LOG_CLIP, LOG_CLIP)

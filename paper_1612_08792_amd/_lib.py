@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmmsp.so")
@@ -58,7 +58,29 @@ _SIGS = {
     "gmmsp_profile_enable": (c_int, [c_void_p, c_int32]),
     "gmmsp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
                                    POINTER(c_int64), c_int32]),
+    "gmmsp_ws_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
+    "gmmsp_ws_attach": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gmmsp_ws_features": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_ws_forward": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
+    "gmmsp_ws_apply": (c_int, [c_void_p, c_void_p, c_uint32, c_void_p]),
+    "gmmsp_ws_targets": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "gmmsp_ws_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float,
+                                    c_int32, c_int32, c_void_p, c_void_p]),
+    "gmmsp_ws_read": (c_int, [c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "gmmsp_ws_write": (c_int, [c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gmmsp_last_error": (c_char_p, []),
+}
+
+WS_NPARAM = 26026
+WS_ALL_OUTPUTS = 0x3FF
+# outputs that move the spatial parameters: mu_x, mu_y, S_xx, S_yy
+WS_SPATIAL_OUTPUTS = 0b0001100011
+# warm-start workspace buffers: index -> (dtype, channels per superpixel)
+WS_BUFFERS = {
+    "feat": (0, "float32", 16), "x0": (1, "bf16", 16), "y1": (2, "bf16", 32),
+    "y2": (3, "bf16", 32), "y3": (4, "bf16", 32), "out": (5, "float32", 16),
+    "tgt": (6, "float32", 16), "g4": (7, "bf16", 16), "g3": (8, "bf16", 32),
+    "g2": (9, "bf16", 32), "g1": (10, "bf16", 32), "grad": (11, "float32", None),
 }
 
 _lib = None

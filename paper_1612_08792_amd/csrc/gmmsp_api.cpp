@@ -128,7 +128,49 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
 
 }  // namespace
 
+namespace {
+
+// warm-start layer table: input / output channels, B-operand shapes of the
+// forward conv and of the input-gradient conv, parameter offsets
+struct WsLayer {
+  int cin, cout, cinp, nk, nt;   // forward: padded input channels, K chunks, column tiles
+  int tcinp, tnk, tnt;           // input gradient (layers 2..4)
+  size_t w_off, b_off;
+};
+constexpr WsLayer kWs[4] = {
+    {16, 32, 16, 5, 2, 0, 0, 0, 0, 4608},
+    {32, 32, 32, 9, 2, 32, 9, 2, 4640, 13856},
+    {32, 32, 32, 9, 2, 32, 9, 2, 13888, 23104},
+    {32, 10, 32, 9, 1, 16, 5, 2, 23136, 26016},
+};
+constexpr int kWsParams = 26026;
+constexpr int kWsMaxSplits = 1024;
+static_assert(kWsParams == GMMSP_WS_NPARAM, "parameter count");
+
+struct WsState {
+  bool attached = false;
+  int32_t* nbr = nullptr;
+  float* feat = nullptr;
+  uint16_t* x0 = nullptr;
+  uint16_t* y[3] = {};
+  float* out = nullptr;
+  float* tgt = nullptr;
+  uint16_t* g4 = nullptr;
+  uint16_t* g[3] = {};
+  uint16_t* wf[4] = {};
+  uint16_t* wt[4] = {};
+  float* part = nullptr;
+  float* grad = nullptr;
+  double* loss_part = nullptr;
+  double* loss_sum = nullptr;
+  size_t sizes[12] = {};
+  void* ptrs[12] = {};
+};
+
+}  // namespace
+
 struct gmmsp_handle {
+  WsState ws;
   int32_t n_img = 0;
   int64_t n_pix = 0;
   std::vector<ImgDesc> img;
@@ -471,6 +513,247 @@ int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream) {
   if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
   hipError_t e = launch_export_candidates(h->P, cand_dev, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_export_candidates");
+  return GMMSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned warm start
+// ---------------------------------------------------------------------------
+namespace {
+
+struct WsLayoutSizes {
+  size_t nbr, feat, x0, y, out, tgt, g4, g, wf[4], wt[4], part, grad, loss_part, loss_sum, total;
+};
+
+WsLayoutSizes ws_sizes(const gmmsp_handle* h) {
+  WsLayoutSizes z{};
+  const size_t n = (size_t)h->P.n_sp;
+  z.nbr = n * 9 * sizeof(int32_t);
+  z.feat = n * 16 * sizeof(float);
+  z.x0 = n * 16 * 2;
+  z.y = n * 32 * 2;
+  z.out = n * 16 * sizeof(float);
+  z.tgt = n * 16 * sizeof(float);
+  z.g4 = n * 16 * 2;
+  z.g = n * 32 * 2;
+  for (int l = 0; l < 4; ++l) {
+    z.wf[l] = (size_t)kWs[l].nk * kWs[l].nt * 64 * 8 * 2;
+    z.wt[l] = (size_t)kWs[l].tnk * kWs[l].tnt * 64 * 8 * 2;
+  }
+  z.part = (size_t)kWsMaxSplits * 32 * 9 * 32 * sizeof(float);
+  z.grad = (size_t)kWsParams * sizeof(float);
+  z.loss_part = (n / 256 + 2) * sizeof(double);
+  z.loss_sum = sizeof(double);
+  size_t t = 0;
+  auto add = [&](size_t b) { t = align256(t + b); };
+  add(z.nbr); add(z.feat); add(z.x0); for (int i = 0; i < 3; ++i) add(z.y);
+  add(z.out); add(z.tgt); add(z.g4); for (int i = 0; i < 3; ++i) add(z.g);
+  for (int l = 0; l < 4; ++l) { add(z.wf[l]); add(z.wt[l]); }
+  add(z.part); add(z.grad); add(z.loss_part); add(z.loss_sum);
+  z.total = t;
+  return z;
+}
+
+int ws_check(gmmsp_handle* h) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (!h->ws.attached) return fail(GMMSP_E_STATE, "warm-start workspace not attached");
+  return GMMSP_OK;
+}
+
+int ws_range(gmmsp_handle* h, int32_t b0, int32_t b1, int* p0, int* p1) {
+  if (b0 < 0 || b1 > h->n_img || b0 >= b1) return fail(GMMSP_E_INVAL, "image range [%d, %d)", b0, b1);
+  *p0 = h->img[b0].sp_off;
+  *p1 = b1 < h->n_img ? h->img[b1].sp_off : h->P.n_sp;
+  return GMMSP_OK;
+}
+
+hipError_t ws_prep_all(gmmsp_handle* h, const float* params, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+    const WsLayer& L = kWs[l];
+    e = ws_launch_prep(params + L.w_off, L.cout, L.cin, L.cinp, L.nk, L.nt, 0, h->ws.wf[l], s);
+    if (e == hipSuccess && l > 0)
+      e = ws_launch_prep(params + L.w_off, L.cout, L.cin, L.tcinp, L.tnk, L.tnt, 1, h->ws.wt[l], s);
+  }
+  return e;
+}
+
+hipError_t ws_forward_range(gmmsp_handle* h, const float* params, int p0, int p1, hipStream_t s) {
+  WsState& W = h->ws;
+  hipError_t e = ws_prep_all(h, params, s);
+  const uint16_t* in = W.x0;
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    e = ws_launch_conv(l + 1, 0, W.nbr, in, W.wf[l], params + kWs[l].b_off, kWs[l].cout, nullptr,
+                       W.y[l], nullptr, p0, p1, s);
+    in = W.y[l];
+  }
+  if (e == hipSuccess)
+    e = ws_launch_conv(4, 1, W.nbr, in, W.wf[3], params + kWs[3].b_off, kWs[3].cout, nullptr,
+                       nullptr, W.out, p0, p1, s);
+  return e;
+}
+
+}  // namespace
+
+int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
+  if (!h || !bytes) return fail(GMMSP_E_INVAL, "null pointer");
+  *bytes = ws_sizes(h).total;
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream) {
+  if (!h || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
+  const WsLayoutSizes z = ws_sizes(h);
+  if (bytes < z.total) return fail(GMMSP_E_SIZE, "warm-start workspace %zu < %zu bytes", bytes, z.total);
+  WsState& W = h->ws;
+  char* b = (char*)ws_dev;
+  size_t t = 0;
+  auto take = [&](size_t n) { void* p = b + t; t = align256(t + n); return p; };
+  W.nbr = (int32_t*)take(z.nbr);
+  W.feat = (float*)take(z.feat);
+  W.x0 = (uint16_t*)take(z.x0);
+  for (int i = 0; i < 3; ++i) W.y[i] = (uint16_t*)take(z.y);
+  W.out = (float*)take(z.out);
+  W.tgt = (float*)take(z.tgt);
+  W.g4 = (uint16_t*)take(z.g4);
+  for (int i = 0; i < 3; ++i) W.g[i] = (uint16_t*)take(z.g);
+  for (int l = 0; l < 4; ++l) {
+    W.wf[l] = (uint16_t*)take(z.wf[l]);
+    W.wt[l] = (uint16_t*)take(z.wt[l]);
+  }
+  W.part = (float*)take(z.part);
+  W.grad = (float*)take(z.grad);
+  W.loss_part = (double*)take(z.loss_part);
+  W.loss_sum = (double*)take(z.loss_sum);
+  void* ptrs[12] = {W.feat, W.x0, W.y[0], W.y[1], W.y[2], W.out, W.tgt, W.g4, W.g[2], W.g[1], W.g[0], W.grad};
+  size_t sizes[12] = {z.feat, z.x0, z.y, z.y, z.y, z.out, z.tgt, z.g4, z.g, z.g, z.g, z.grad};
+  for (int i = 0; i < 12; ++i) {
+    W.ptrs[i] = ptrs[i];
+    W.sizes[i] = sizes[i];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ws_launch_nbr(h->P, W.nbr, s);
+  if (e == hipSuccess) e = hipMemsetAsync(W.tgt, 0, z.tgt, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_attach");
+  W.attached = true;
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_features(gmmsp_handle* h, const float* lab_dev, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipError_t e = ws_launch_features(h->P, lab_dev, h->ws.feat, h->ws.x0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_features");
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_forward(gmmsp_handle* h, const float* params_dev, int32_t b0, int32_t b1,
+                     void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!params_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  int p0, p1;
+  rc = ws_range(h, b0, b1, &p0, &p1);
+  if (rc) return rc;
+  hipError_t e = ws_forward_range(h, params_dev, p0, p1, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_forward");
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_apply(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  // theta^0 rows are staged in the partials area, which the next pass overwrites
+  double* rows = h->P.part;
+  hipError_t e = ws_launch_apply(h->P, lab_dev, h->ws.out, output_mask, rows, s);
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_set_params(h->P, rows, s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_apply");
+  h->initialised = true;
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_targets(gmmsp_handle* h, const float* lab_dev, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipError_t e = ws_launch_targets(h->P, lab_dev, h->ws.tgt, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_targets");
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_train_step(gmmsp_handle* h, float* params_dev, float* m_dev, float* v_dev,
+                        int32_t step, float lr, int32_t b0, int32_t b1, double* loss_host,
+                        void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!params_dev || !m_dev || !v_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (step < 1 || !(lr > 0)) return fail(GMMSP_E_INVAL, "step must be >= 1 and lr > 0");
+  int p0, p1;
+  rc = ws_range(h, b0, b1, &p0, &p1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  WsState& W = h->ws;
+  const float scale = 1.0f / (float)(p1 - p0);
+  const int nchunks = (p1 - p0 + 31) / 32;
+  const int splits = nchunks < 4 * kWsMaxSplits ? (nchunks + 3) / 4 : kWsMaxSplits;
+  const int cps = (nchunks + splits - 1) / splits;
+  hipError_t e = ws_forward_range(h, params_dev, p0, p1, s);
+  if (e == hipSuccess) e = ws_launch_loss(W.out, W.tgt, W.g4, p0, p1, W.loss_part, W.loss_sum, s);
+  // layer inputs and output gradients, from the last layer down
+  const uint16_t* xin[4] = {W.x0, W.y[0], W.y[1], W.y[2]};
+  uint16_t* gout[4] = {W.g[0], W.g[1], W.g[2], W.g4};
+  const int gc[4] = {32, 32, 32, 16};
+  for (int l = 3; l >= 0 && e == hipSuccess; --l) {
+    const WsLayer& L = kWs[l];
+    e = ws_launch_dw(l + 1, W.nbr, gout[l], xin[l], W.part, splits, cps, p0, p1, s);
+    if (e == hipSuccess)
+      e = ws_launch_reduce_dw(W.part, splits, gc[l], L.cout, 9 * L.cin, scale, W.grad + L.w_off, s);
+    if (e == hipSuccess) e = ws_launch_db(gout[l], gc[l], L.cout, p0, p1, scale, W.grad + L.b_off, s);
+    if (e == hipSuccess && l > 0)
+      e = ws_launch_conv(l + 1, 2, W.nbr, gout[l], W.wt[l], nullptr, L.cin, xin[l], gout[l - 1],
+                         nullptr, p0, p1, s);
+  }
+  const float b1c = 1.0f - powf(0.9f, (float)step), b2c = 1.0f - powf(0.999f, (float)step);
+  if (e == hipSuccess)
+    e = ws_launch_adam(params_dev, m_dev, v_dev, W.grad, kWsParams, lr, 0.9f, 0.999f, 1e-8f, b1c,
+                       b2c, s);
+  if (e == hipSuccess && loss_host) {
+    double ls = 0.0;
+    e = hipMemcpyAsync(&ls, W.loss_sum, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    *loss_host = ls / ((double)(p1 - p0) * 10.0);
+  }
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_train_step");
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_read(gmmsp_handle* h, int32_t which, void* host, size_t bytes, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!host || which < 0 || which >= 12) return fail(GMMSP_E_INVAL, "bad buffer or pointer");
+  if (bytes > h->ws.sizes[which]) return fail(GMMSP_E_SIZE, "read past the buffer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(host, h->ws.ptrs[which], bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_read");
+  return GMMSP_OK;
+}
+
+int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t bytes, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!host || which < 0 || which >= 12) return fail(GMMSP_E_INVAL, "bad buffer or pointer");
+  if (bytes > h->ws.sizes[which]) return fail(GMMSP_E_SIZE, "write past the buffer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(h->ws.ptrs[which], host, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_write");
   return GMMSP_OK;
 }
 

@@ -87,4 +87,27 @@ hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hip
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s);
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
 
+// Warm-start network launchers (gmmsp_warmstart.hip).
+hipError_t ws_launch_nbr(const DevPtrs& P, int32_t* nbr, hipStream_t s);
+hipError_t ws_launch_features(const DevPtrs& P, const float* lab, float* feat, uint16_t* x0,
+                              hipStream_t s);
+hipError_t ws_launch_prep(const float* W, int cout, int cin, int cinp, int nk, int nt,
+                          int transposed, uint16_t* wb, hipStream_t s);
+hipError_t ws_launch_conv(int layer, int mode, const int32_t* nbr, const uint16_t* in,
+                          const uint16_t* wb, const float* bias, int cout, const uint16_t* mask,
+                          uint16_t* out_bf, float* out_f, int p0, int p1, hipStream_t s);
+hipError_t ws_launch_dw(int layer, const int32_t* nbr, const uint16_t* g, const uint16_t* x,
+                        float* part, int splits, int cps, int p0, int p1, hipStream_t s);
+hipError_t ws_launch_reduce_dw(const float* part, int splits, int gc, int cout, int ncol,
+                               float scale, float* grad, hipStream_t s);
+hipError_t ws_launch_db(const uint16_t* g, int gc, int cout, int p0, int p1, float scale,
+                        float* db, hipStream_t s);
+hipError_t ws_launch_loss(const float* out, const float* tgt, uint16_t* g4, int p0, int p1,
+                          double* loss_part, double* loss_sum, hipStream_t s);
+hipError_t ws_launch_adam(float* w, float* m, float* v, const float* grad, int n, float lr,
+                          float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t ws_launch_apply(const DevPtrs& P, const float* lab, const float* out, uint32_t mask,
+                           double* rows, hipStream_t s);
+hipError_t ws_launch_targets(const DevPtrs& P, const float* lab, float* tgt, hipStream_t s);
+
 }  // namespace gmmsp

@@ -164,6 +164,72 @@ class GMMSP:
         return dict(estep_ms=ms.value, launches=n.value, pixel_evals=px.value,
                     pair_evals=pr.value)
 
+    # -- learned warm start ----------------------------------------------------
+    def ws_attach(self):
+        """Allocate (torch) and attach the warm-start workspace."""
+        if getattr(self, "ws_workspace", None) is not None:
+            return
+        nbytes = c_size_t(0)
+        check(lib().gmmsp_ws_workspace_bytes(self.handle, byref(nbytes)))
+        self.ws_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        check(lib().gmmsp_ws_attach(self.handle, c_void_p(_ptr(self.ws_workspace)), nbytes.value,
+                                    c_void_p(self._stream())))
+
+    def _params(self, params: torch.Tensor) -> c_void_p:
+        if params.dtype != torch.float32 or not params.is_contiguous() or \
+                params.numel() != _lib.WS_NPARAM or params.device != self.device:
+            raise ValueError(f"parameters must be {_lib.WS_NPARAM} contiguous float32 on the device")
+        return c_void_p(_ptr(params))
+
+    def ws_features(self, lab: torch.Tensor):
+        check(lib().gmmsp_ws_features(self.handle, self._lab(lab), c_void_p(self._stream())))
+
+    def ws_forward(self, params: torch.Tensor, b0: int = 0, b1: int | None = None):
+        b1 = self.n_images if b1 is None else b1
+        check(lib().gmmsp_ws_forward(self.handle, self._params(params), b0, b1,
+                                     c_void_p(self._stream())))
+
+    def ws_apply(self, lab: torch.Tensor, mask: int = _lib.WS_ALL_OUTPUTS):
+        check(lib().gmmsp_ws_apply(self.handle, self._lab(lab), int(mask),
+                                   c_void_p(self._stream())))
+
+    def ws_targets(self, lab: torch.Tensor):
+        check(lib().gmmsp_ws_targets(self.handle, self._lab(lab), c_void_p(self._stream())))
+
+    def ws_train_step(self, params, m, v, step: int, lr: float, b0: int = 0, b1=None,
+                      want_loss: bool = True):
+        b1 = self.n_images if b1 is None else b1
+        loss = c_double(0.0)
+        for t in (m, v):
+            self._params(t)
+        check(lib().gmmsp_ws_train_step(self.handle, self._params(params), c_void_p(_ptr(m)),
+                                        c_void_p(_ptr(v)), int(step), float(lr), b0, b1,
+                                        byref(loss) if want_loss else None,
+                                        c_void_p(self._stream())))
+        return loss.value if want_loss else None
+
+    def ws_read(self, name: str) -> np.ndarray:
+        idx, dt, ch = _lib.WS_BUFFERS[name]
+        n = _lib.WS_NPARAM if ch is None else self.n_superpixels * ch
+        if dt == "bf16":
+            raw = np.empty(n, dtype=np.uint16)
+            check(lib().gmmsp_ws_read(self.handle, idx, c_void_p(raw.ctypes.data), raw.nbytes,
+                                      c_void_p(self._stream())))
+            out = (raw.astype(np.uint32) << 16).view(np.float32)
+        else:
+            out = np.empty(n, dtype=np.float32)
+            check(lib().gmmsp_ws_read(self.handle, idx, c_void_p(out.ctypes.data), out.nbytes,
+                                      c_void_p(self._stream())))
+        return out if ch is None else out.reshape(self.n_superpixels, ch)
+
+    def ws_write(self, name: str, values: np.ndarray):
+        idx, dt, ch = _lib.WS_BUFFERS[name]
+        if dt != "float32":
+            raise ValueError("only float32 buffers can be written")
+        a = np.ascontiguousarray(np.asarray(values, dtype=np.float32))
+        check(lib().gmmsp_ws_write(self.handle, idx, c_void_p(a.ctypes.data), a.nbytes,
+                                   c_void_p(self._stream())))
+
     # -- helpers -------------------------------------------------------------
     def image_slice(self, b: int) -> slice:
         return slice(int(self.pix_off[b]), int(self.pix_off[b + 1]))

@@ -1,0 +1,108 @@
+"""Train the warm-start network on the 481x321 training set and evaluate it.
+
+    python -m paper_1612_08792_amd.train_warmstart [--images 4096] [--out PATH]
+
+Training set: synthetic 481x321 Voronoi-Lab images (40 regions, sigma 3,
+K = 400) with seeds 10000.., targets = the parameters of plain EM after 24
+passes (produced by the library on the GPU).  Held-out set: seeds 20000..
+(256 images).  Writes the weights (.npz) and an evaluation summary (.json):
+passes of warm-started and plain EM to the plain-EM log-likelihood within 1e-4
+relative, passes to the 1e-5 relative-change stop rule, and the final
+log-likelihoods."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_1612_08792_amd import _lib, warmstart  # noqa: E402
+from paper_1612_08792_amd.gmmsp import GMMSP  # noqa: E402
+
+# outputs applied at inference: the means and the spatial scales (the colour
+# log-scales are not predictable from the inputs and are left at lambda^2)
+MASK = 0b0001111111
+TARGET_PASSES = 24
+DEFAULT_OUT = os.path.join(warmstart.WEIGHTS_DIR, "ws_481x321.npz")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def evaluate(params, dev, n_test=256, first_seed=20000, cap=200, tol=1e-5, mask=MASK):
+    ims = [synth.config4_image(first_seed + i, dev) for i in range(n_test)]
+    lab = synth.pack_batch(ims).to(dev)
+    sizes = [(im.W, im.H) for im in ims]
+    plain = GMMSP(sizes, K=400, device=dev)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    plain.init_seeds(lab)
+    it_p = plain.em_iterate(lab, cap, tol)
+    torch.cuda.synchronize(dev)
+    t_plain = time.perf_counter() - t0
+    warm = GMMSP(sizes, K=400, device=dev)
+    warm.ws_attach()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    warmstart.warm_start(warm, lab, params, mask)
+    it_w = warm.em_iterate(lab, cap, tol)
+    torch.cuda.synchronize(dev)
+    t_warm = time.perf_counter() - t0
+    tp, tw, dl = [], [], []
+    for b in range(n_test):
+        hp, hw = plain.ll_history(b), warm.ll_history(b)
+        tp.append(warmstart.passes_to_target(hp, hp[-1]))
+        tw.append(warmstart.passes_to_target(hw, hp[-1]))
+        dl.append((hw[-1] - hp[-1]) / abs(hp[-1]))
+    return dict(images=n_test, mask=mask,
+                passes_to_plain_L_plain=float(np.mean(tp)),
+                passes_to_plain_L_warm=float(np.mean(tw)),
+                passes_to_stop_plain=float(np.mean(it_p)),
+                passes_to_stop_warm=float(np.mean(it_w)),
+                time_to_stop_plain_s=t_plain, time_to_stop_warm_s=t_warm,
+                final_L_rel_diff_mean=float(np.mean(dl)),
+                final_L_rel_diff_min=float(np.min(dl)),
+                final_L_rel_diff_max=float(np.max(dl)))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--images", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch-images", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ims = [synth.config4_image(10000 + i, dev) for i in range(args.images)]
+    log(f"generated {len(ims)} training images in {time.time() - t0:.1f} s")
+    params, info = warmstart.train(ims, dev, epochs=args.epochs, batch_images=args.batch_images,
+                                   lr=args.lr, target_passes=TARGET_PASSES,
+                                   log=lambda s: None)
+    log(f"trained: loss {info['losses'][0]:.4f} -> {info['losses'][-1]:.4f} in {info['t_total']:.1f} s")
+    del ims
+    ev = evaluate(params, dev)
+    log(json.dumps(ev))
+    info.update(target_passes=TARGET_PASSES, epochs=args.epochs, batch_images=args.batch_images,
+                lr=args.lr, mask=MASK)
+    warmstart.save(params, args.out, info)
+    with open(os.path.splitext(args.out)[0] + "_eval.json", "w") as f:
+        json.dump(dict(training={k: v for k, v in info.items() if k != "losses"},
+                       loss_first=info["losses"][0], loss_last=info["losses"][-1],
+                       heldout=ev), f, indent=1)
+    log(f"saved {args.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -10,8 +10,8 @@ from oracle import ws_oracle as WS
 
 
 def test_param_count():
-    # 8*9*32+32 + 2*(32*9*32+32) + 32*9*10+10
-    assert WS.param_count() == 2336 + 2 * 9248 + 2890
+    # 16*9*32+32 + 2*(32*9*32+32) + 32*9*10+10
+    assert WS.param_count() == 4640 + 2 * 9248 + 2890
 
 
 def test_conv3x3_matches_scipy_correlate():
@@ -61,24 +61,49 @@ def test_features_of_constant_cells_and_border_channel():
     np.testing.assert_allclose(f[..., 1], -0.5)
     np.testing.assert_allclose(f[..., 2], 0.25)
     np.testing.assert_allclose(f[..., 3:6], 0.0, atol=1e-12)
+    np.testing.assert_allclose(f[..., 7:16], 0.0, atol=1e-12)
     # distance to the border in cells, capped at 3, over 3: a 5 x 3 grid
     np.testing.assert_allclose(f[..., 6] * 3, [[0, 0, 0, 0, 0], [0, 1, 1, 1, 0], [0, 0, 0, 0, 0]])
 
 
-def test_zero_output_is_grid_init_with_cell_mean_colour():
+def test_half_cell_and_seed_channels_by_hand():
+    # one 5 x 5 cell: L = 10 x (column), a = 4 x (row), b = 0; h = 2
+    lab = np.zeros((5, 5, 3), np.float32)
+    lab[..., 0] = 10.0 * np.arange(5)[None, :]
+    lab[..., 1] = 4.0 * np.arange(5)[:, None]
+    f = WS.features(lab, 5, 5, 1, 1)[0, 0]
+    # right columns {3, 4} minus left {0, 1}: L 35 - 5 = 30; rows likewise for a: 14 - 2 = 12
+    np.testing.assert_allclose(f[10:13], [30 / 32, 0, 0], atol=1e-12)
+    np.testing.assert_allclose(f[13:16], [0, 12 / 32, 0], atol=1e-12)
+    # seed (2, 2): colour (20, 8, 0), cell mean (20, 8, 0)
+    np.testing.assert_allclose(f[7:10], 0.0, atol=1e-12)
+    np.testing.assert_allclose(f[3], np.std(10.0 * np.arange(5)) / 16)
+
+
+def test_zero_output_is_the_grid_init():
     rng = np.random.default_rng(3)
     lab = rng.uniform(0, 50, (19 * 2, 19 * 3, 3)).astype(np.float32)
-    f = WS.features(lab, 19, 19, 3, 2)
-    rows = WS.theta0_rows(np.zeros((2, 3, 10)), f, 19, 19, 8.0)
+    rows = WS.theta0_rows(np.zeros((2, 3, 10)), lab, 19, 19, 8.0)
     assert rows[4, 0] == 19 + 9 and rows[4, 1] == 19 + 9          # k = (1, 1)
-    np.testing.assert_allclose(rows[4, 2:5], lab[19:38, 19:38].reshape(-1, 3).mean(0), rtol=1e-6)
+    np.testing.assert_array_equal(rows[4, 2:5], lab[28, 28])
     np.testing.assert_allclose(rows[:, [5, 7, 8, 9, 11]], [[361, 361, 64, 64, 64]] * 6)
     assert np.all(rows[:, [6, 10]] == 0)
 
 
+def test_output_mask_zeroes_outputs():
+    rng = np.random.default_rng(5)
+    lab = rng.uniform(0, 50, (30, 40, 3)).astype(np.float32)
+    out = rng.uniform(-1, 1, (3, 4, 10))
+    mask = 0b0001100011          # mu_x, mu_y, S_xx, S_yy only
+    got = WS.theta0_rows(out, lab, 10, 10, 8.0, mask)
+    kept = out * np.array([(mask >> c) & 1 for c in range(10)])
+    np.testing.assert_array_equal(got, WS.theta0_rows(kept, lab, 10, 10, 8.0))
+
+
 def test_targets_invert_theta0():
     rng = np.random.default_rng(4)
-    f = rng.normal(size=(3, 4, 8)) * 0.5
+    lab = rng.uniform(0, 50, (45, 68, 3)).astype(np.float32)
     out = rng.uniform(-2, 2, (3, 4, 10))
-    rows = WS.theta0_rows(out, f, 17, 15, 8.0)
-    np.testing.assert_allclose(WS.targets(rows, f, 17, 15, 8.0), out, rtol=1e-10, atol=1e-12)
+    rows = WS.theta0_rows(out, lab, 17, 15, 8.0)
+    np.testing.assert_allclose(WS.targets(rows, lab, 17, 15, 4, 3, 8.0), out, rtol=1e-10,
+                               atol=1e-12)
