@@ -45,8 +45,10 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic(pixel_evals_per_launch):
-    """HBM bytes per E-step launch from the committed PMC summary, only if it was
-    taken on the current kernel source."""
+    """HBM bytes per E-step launch: bytes per evaluated pixel from the committed
+    PMC measurement (FETCH_SIZE scaled by a plain copy, WRITE_SIZE) times the
+    pixels one launch evaluated here, only if it was taken on the current
+    kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +56,7 @@ def measured_traffic(pixel_evals_per_launch):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_digest():
         return None
-    return t.get("bytes_per_launch")
+    return round(t["bytes_per_pixel_eval"] * pixel_evals_per_launch, 0)
 
 
 WS_MASK = 0b0001111111   # warm-start outputs applied: the means and the spatial scales
