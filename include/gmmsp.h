@@ -152,6 +152,29 @@ int gmmsp_export_responsibilities(gmmsp_handle* h, const float* lab_dev, float* 
                                   void* stream);
 int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream);
 
+/* Schedule of the statistics pass: how many 64-lane waves share one v_x x v_y
+ * cell (1, 2 or 4; default 1).  More waves per cell raise the parallelism of
+ * small batches; every schedule gives the same result up to the grouping of the
+ * FP64 sums (each schedule is itself bitwise repeatable). */
+#define GMMSP_MAX_WAVES_PER_CELL 4
+int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell);
+int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
+
+/* Autotuner: times `passes` statistics passes (after one untimed pass) from the
+ * grid initialisation for each schedule 1, 2, 4 with HIP events on `stream`,
+ * keeps the fastest (ties to fewer waves), and leaves the handle initialised
+ * by gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times. */
+int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
+                   int32_t* chosen, void* stream);
+
+/* Graph replay: with passes > 0, gmmsp_em_iterate runs whole chunks of
+ * `passes` em passes as one captured hipGraph launch each (captured on first
+ * use for the given image buffer, tolerance and schedule, on a private stream
+ * ordered after the caller's), the stop test being read between chunks; the
+ * remainder of max_iters runs as single launches.  0 (default) turns it off.
+ * Not used while kernel timing is enabled. */
+int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes);
+
 /* Kernel timing for roofline reporting.  While enabled, gmmsp_em_iterate
  * brackets every launch of the E-step/statistics kernel with HIP events on the
  * caller's stream.  gmmsp_profile_read returns, since the last reset: the summed

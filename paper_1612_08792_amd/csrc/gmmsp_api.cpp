@@ -117,7 +117,7 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
   L->sp = o;      o = align256(o + sizeof(SpDesc) * n_sp);
   L->theta = o;   o = align256(o + sizeof(double) * kThetaRow * n_sp);
   L->rec = o;     o = align256(o + sizeof(float) * kRecFloats * kSlots * n_cell);
-  L->part = o;    o = align256(o + sizeof(double) * kPartStride * n_cell);
+  L->part = o;    o = align256(o + sizeof(double) * kPartStride * kMaxWpc * n_cell);
   L->n_done = o;  o = align256(o + sizeof(int32_t));
   L->total = o;
   L->n_cell = (int32_t)n_cell;
@@ -181,6 +181,15 @@ struct gmmsp_handle {
   static constexpr int kRing = 4;
   int32_t* done_ring = nullptr;
   hipEvent_t done_ev[kRing] = {};
+  // graph replay of em passes: a private stream joined to the caller's by events
+  int32_t graph_passes = 0;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const float* g_lab = nullptr;
+  double g_tol = 0.0;
+  int32_t g_len = 0, g_wpc = 0;
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -192,6 +201,11 @@ struct gmmsp_handle {
     for (hipEvent_t e : done_ev)
       if (e) (void)hipEventDestroy(e);
     if (done_ring) (void)hipHostFree(done_ring);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (gev_in) (void)hipEventDestroy(gev_in);
+    if (gev_out) (void)hipEventDestroy(gev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
   }
 };
 
@@ -269,6 +283,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.n_img = n_images;
   P.n_cell = L.n_cell;
   P.n_sp = L.n_sp;
+  P.wpc = 1;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -361,6 +376,81 @@ int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
   return GMMSP_OK;
 }
 
+namespace {
+
+// Capture `len` em passes into a graph on the handle's private stream.
+int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t len) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
+  for (int32_t i = 0; i < len && e == hipSuccess; ++i) {
+    e = launch_estep_stats(h->P, lab, h->gstream);
+    if (e == hipSuccess) e = launch_ll_update(h->P, rel_tol, h->gstream);
+    if (e == hipSuccess) e = launch_finalize(h->P, h->gstream);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(h->gstream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e, "graph capture");
+  }
+  h->graph = g;
+  h->g_lab = lab;
+  h->g_tol = rel_tol;
+  h->g_len = len;
+  h->g_wpc = h->P.wpc;
+  return GMMSP_OK;
+}
+
+// Run whole chunks of graph_passes passes as graph launches; the stop test of
+// each chunk is read while the next chunk is already queued.
+int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, double rel_tol,
+                     hipStream_t s, int32_t* done_iters, bool* all_done) {
+  hipError_t e = hipSuccess;
+  if (!h->gstream) e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking);
+  if (e == hipSuccess && !h->gev_in) e = hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming);
+  if (e == hipSuccess && !h->gev_out) e = hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "graph stream");
+  const int32_t G = h->graph_passes;
+  if (!h->gexec || h->g_lab != lab || h->g_tol != rel_tol || h->g_len != G || h->g_wpc != h->P.wpc) {
+    int rc = capture_passes(h, lab, rel_tol, G);
+    if (rc) return rc;
+  }
+  e = hipEventRecord(h->gev_in, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->gstream, h->gev_in, 0);
+  int32_t it = 0, chunk = 0;
+  *all_done = false;
+  while (e == hipSuccess && it + G <= max_iters) {
+    e = hipGraphLaunch(h->gexec, h->gstream);
+    if (e != hipSuccess) break;
+    it += G;
+    if (rel_tol > 0.0) {
+      const int slot = chunk % gmmsp_handle::kRing;
+      e = hipMemcpyAsync(&h->done_ring[slot], h->P.n_done, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         h->gstream);
+      if (e == hipSuccess) e = hipEventRecord(h->done_ev[slot], h->gstream);
+      if (e == hipSuccess && chunk >= 1) {
+        const int prev = (chunk - 1) % gmmsp_handle::kRing;
+        e = hipEventSynchronize(h->done_ev[prev]);
+        if (e == hipSuccess && h->done_ring[prev] >= h->n_img) *all_done = true;
+      }
+      if (*all_done) break;
+    }
+    ++chunk;
+  }
+  if (e == hipSuccess) e = hipEventRecord(h->gev_out, h->gstream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, h->gev_out, 0);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  *done_iters = it;
+  return GMMSP_OK;
+}
+
+}  // namespace
+
 int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, double rel_tol,
                      int32_t* iters_host, void* stream) {
   if (!h || !lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
@@ -386,7 +476,14 @@ int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, d
     }
   }
   int32_t launched = 0;
-  for (int32_t it = 0; it < max_iters; ++it) {
+  int32_t it = 0;
+  bool all_done = false;
+  if (h->graph_passes > 0 && max_iters >= h->graph_passes && !h->profile) {
+    int rc = run_graph_chunks(h, lab_dev, max_iters, rel_tol, s, &it, &all_done);
+    if (rc) return rc;
+    launched = it;
+  }
+  for (; it < max_iters && !all_done; ++it) {
     if (h->profile) e = hipEventRecord(h->ev[2 * it], s);
     if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
     if (e == hipSuccess && h->profile) e = hipEventRecord(h->ev[2 * it + 1], s);
@@ -483,6 +580,73 @@ int gmmsp_export_responsibilities(gmmsp_handle* h, const float* lab_dev, float* 
   if (!h->initialised) return fail(GMMSP_E_STATE, "handle not initialised");
   hipError_t e = launch_export_R(h->P, lab_dev, R_dev, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_export_responsibilities");
+  return GMMSP_OK;
+}
+
+int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (waves_per_cell != 1 && waves_per_cell != 2 && waves_per_cell != 4)
+    return fail(GMMSP_E_INVAL, "waves per cell must be 1, 2 or 4");
+  h->P.wpc = waves_per_cell;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell) {
+  if (!h || !waves_per_cell) return fail(GMMSP_E_INVAL, "null pointer");
+  *waves_per_cell = h->P.wpc;
+  return GMMSP_OK;
+}
+
+int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (passes < 0 || passes > 256) return fail(GMMSP_E_INVAL, "graph passes %d outside [0, 256]", passes);
+  h->graph_passes = passes;
+  return GMMSP_OK;
+}
+
+int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
+                   int32_t* chosen, void* stream) {
+  if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
+  if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t cand[3] = {1, 2, 4};
+  double best = 0.0;
+  int32_t pick = 1;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    h->P.wpc = cand[c];
+    e = launch_reset_state(h->P, s);
+    if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+    double tot = 0.0;
+    // one untimed pass, then `passes` timed ones
+    for (int32_t i = 0; i <= passes && e == hipSuccess; ++i) {
+      e = hipEventRecord(a, s);
+      if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = launch_ll_update(h->P, 0.0, s);
+      if (e == hipSuccess) e = launch_finalize(h->P, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (i > 0) tot += ms;
+    }
+    if (ms_host) ms_host[c] = tot;
+    if (c == 0 || tot < best) {
+      best = tot;
+      pick = cand[c];
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  h->P.wpc = pick;
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune");
+  h->initialised = true;
+  *chosen = pick;
   return GMMSP_OK;
 }
 

@@ -15,7 +15,8 @@ constexpr int kLLSlot = 117;
 constexpr int kRecFloats = 16;     // floats per cell-slot record
 constexpr int kThetaRow = 13;      // doubles per superpixel in the FP64 master
 constexpr int kLLCap = 4096;       // log-likelihood history entries per image
-constexpr int kCellsPerBlock = 4;  // one 64-lane wave per cell, 4 waves per block
+constexpr int kWavesPerBlock = 4;  // 64-lane waves per block of the per-cell kernels
+constexpr int kMaxWpc = 4;         // largest number of waves sharing one cell
 
 // Cell-slot record: the parameters of the superpixel in slot s of cell c, in
 // float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
@@ -70,9 +71,10 @@ struct DevPtrs {
   const SpDesc* sp;
   double* theta;            // [n_sp][kThetaRow] FP64 master
   float* rec;               // [n_cell][9][kRecFloats]
-  double* part;             // [n_cell][kPartStride]
+  double* part;             // [kMaxWpc][n_cell][kPartStride]: one set per cell wave
   int32_t* n_done;          // images that have stopped
   int32_t n_img, n_cell, n_sp;
+  int32_t wpc;              // waves per cell of the statistics pass (1, 2 or 4)
 };
 
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.

@@ -343,11 +343,12 @@ __device__ __forceinline__ void wave_reduce_scatter_117(float (&v)[CAP], int lan
 
 // record offsets held in vector registers for the whole cell (see VOff)
 #ifndef GMMSP_VOFF
-#define GMMSP_VOFF 1
+#define GMMSP_VOFF 0
 #endif
 
+// 3 waves per SIMD measured fastest for the statistics pass (168 VGPRs)
 #ifndef GMMSP_WAVES_PER_EU
-#define GMMSP_WAVES_PER_EU 0
+#define GMMSP_WAVES_PER_EU 3
 #endif
 #if GMMSP_WAVES_PER_EU > 0
 #define CELLS_ATTR __attribute__((amdgpu_waves_per_eu(GMMSP_WAVES_PER_EU)))
@@ -457,13 +458,18 @@ __device__ __forceinline__ void advance(int& row, int& col, int dr, int dc, int 
   }
 }
 
-template <int MODE>
+template <int MODE, int WPC = 1>
 __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float* __restrict__ lab,
                                                           int32_t* __restrict__ out_i,
                                                           float* __restrict__ out_f) {
   const int lane = threadIdx.x & 63;
-  const int cell = __builtin_amdgcn_readfirstlane(
-      (int)(blockIdx.x * kCellsPerBlock + (threadIdx.x >> 6)));
+  // the statistics pass may share a cell among WPC waves (wave sub takes the
+  // pixel rounds sub, sub + WPC, ...); the other modes use one wave per cell
+  constexpr int wpc = WPC;
+  const int gw = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
+  const int cell = __builtin_amdgcn_readfirstlane(gw / wpc);
+  const int sub = __builtin_amdgcn_readfirstlane(gw - cell * wpc);
   if (cell >= P.n_cell) return;
   const AS4 CellDesc* cdp = cptr(P.cell) + cell;
   const int b = cdp->img, ccx = cdp->cx, ccy = cdp->cy;
@@ -506,15 +512,17 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     // lane masked past the end); a last round of at most 64 pixels runs after
     // the loop, one pixel per lane, so the loop body has a single path and the
     // accumulators stay in place.
-    int r1 = lane / w, c1 = lane - r1 * w;
-    int r2 = (lane + 64) / w, c2 = (lane + 64) - r2 * w;
-    const int dr = 128 / w, dc = 128 - (128 / w) * w;
+    const int q0 = 128 * sub + lane;  // this wave's first pixel
+    int r1 = q0 / w, c1 = q0 - r1 * w;
+    int r2 = (q0 + 64) / w, c2 = (q0 + 64) - r2 * w;
+    const int step = 128 * wpc;
+    const int dr = step / w, dc = step - (step / w) * w;
     const int n_pair = npix > 64 ? (npix - 64 + 127) >> 7 : 0;  // rounds with base + 64 < npix
 #if GMMSP_VOFF
     VOff vo;
     load_voff(rec0, vo);
 #endif
-    for (int rd = 0; rd < n_pair; ++rd) {
+    for (int rd = sub; rd < n_pair; rd += wpc) {
       const int base = rd << 7;
       // The 144 record floats do not fit the scalar registers; an opaque zero
       // offset keeps the compiler from hoisting them out of the loop, so each
@@ -541,7 +549,8 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       advance(r1, c1, dr, dc, w);
       advance(r2, c2, dr, dc, w);
     }
-    if ((n_pair << 7) + lane < npix) {
+    // the last round (at most 64 pixels) falls to the wave whose turn it is
+    if (n_pair % wpc == sub && (n_pair << 7) + lane < npix) {
       const float* q1 = img + 3 * (r1 * W + c1);
       const float xr[1] = {(float)c1}, yr[1] = {(float)r1};
       const float L[1] = {q1[0]}, A[1] = {q1[1]}, B[1] = {q1[2]};
@@ -553,7 +562,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     }
     wave_reduce_scatter_117(acc, lane);
     const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
-    double* part = P.part + (size_t)cell * kPartStride;
+    double* part = P.part + ((size_t)sub * P.n_cell + cell) * kPartStride;
     part[r] = (double)acc[0];
     if (64 + r < kSlots * kStats) part[64 + r] = (double)acc[1];
   } else {
@@ -596,14 +605,17 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     double ll = (double)llacc;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
-    if (lane == 0) P.part[(size_t)cell * kPartStride + kLLSlot] = kLn2 * ll + (double)npix * Ip->lncmax;
+    // each wave of a cell adds its own pixels' share; the constant term once
+    const double cst = sub == 0 ? (double)npix * Ip->lncmax : 0.0;
+    if (lane == 0) P.part[((size_t)sub * P.n_cell + cell) * kPartStride + kLLSlot] = kLn2 * ll + cst;
   }
 }
 
 // ---------------------------------------------------------------------------
 // L(theta^t) per image and the stop rule; one block per image
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass) {
+__global__ __launch_bounds__(256) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
+                                                   int nsub) {
   __shared__ double red[256];
   const int b = blockIdx.x;
   const ImgDesc* I = P.img + b;
@@ -611,9 +623,10 @@ __global__ __launch_bounds__(256) void k_ll_reduce(DevPtrs P, double rel_tol, in
   const int done = st->done;
   if (!final_pass && done) return;
   const int ncells = I->ncells;
-  const double* part = P.part + (size_t)I->cell_off * kPartStride + kLLSlot;
   double s = 0.0;
-  for (int c = threadIdx.x; c < ncells; c += 256) s += part[(size_t)c * kPartStride];
+  for (int c = threadIdx.x; c < ncells; c += 256)
+    for (int u = 0; u < nsub; ++u)
+      s += P.part[((size_t)u * P.n_cell + I->cell_off + c) * kPartStride + kLLSlot];
   red[threadIdx.x] = s;
   __syncthreads();
 #pragma unroll
@@ -665,24 +678,27 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
       const int cx = d.kx - dx, cy = d.ky - dy;
       if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) continue;
       const int slot = 3 * (dy + 1) + (dx + 1);
-      const double* q = P.part + (size_t)(I.cell_off + cy * I.ncx + cx) * kPartStride + slot * kStats;
       // move the spatial moments from the cell origin to the superpixel's
       // own cell origin: x' = x + ox with ox = (cx - kx) v_x
       const double ox = (double)(-dx) * I.vx, oy = (double)(-dy) * I.vy;
-      const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
-      acc[S_N] += n;
-      acc[S_X] += sx + ox * n;
-      acc[S_Y] += sy + oy * n;
-      acc[S_L] += q[S_L];
-      acc[S_A] += q[S_A];
-      acc[S_B] += q[S_B];
-      acc[S_XX] += q[S_XX] + 2.0 * ox * sx + ox * ox * n;
-      acc[S_XY] += q[S_XY] + ox * sy + oy * sx + ox * oy * n;
-      acc[S_YY] += q[S_YY] + 2.0 * oy * sy + oy * oy * n;
-      acc[S_LL] += q[S_LL];
-      acc[S_AA] += q[S_AA];
-      acc[S_AB] += q[S_AB];
-      acc[S_BB] += q[S_BB];
+      for (int u = 0; u < P.wpc; ++u) {
+        const double* q = P.part + ((size_t)u * P.n_cell + I.cell_off + cy * I.ncx + cx) * kPartStride +
+                          slot * kStats;
+        const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
+        acc[S_N] += n;
+        acc[S_X] += sx + ox * n;
+        acc[S_Y] += sy + oy * n;
+        acc[S_L] += q[S_L];
+        acc[S_A] += q[S_A];
+        acc[S_B] += q[S_B];
+        acc[S_XX] += q[S_XX] + 2.0 * ox * sx + ox * ox * n;
+        acc[S_XY] += q[S_XY] + ox * sy + oy * sx + ox * oy * n;
+        acc[S_YY] += q[S_YY] + 2.0 * oy * sy + oy * oy * n;
+        acc[S_LL] += q[S_LL];
+        acc[S_AA] += q[S_AA];
+        acc[S_AB] += q[S_AB];
+        acc[S_BB] += q[S_BB];
+      }
     }
   }
   double* row = P.theta + (size_t)sp * kThetaRow;
@@ -741,13 +757,21 @@ hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s
 }
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
-  hipLaunchKernelGGL(k_cells<M_STATS>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256), 0,
-                     s, P, lab, (int32_t*)nullptr, (float*)nullptr);
+  const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
+  if (P.wpc == 4)
+    hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
+                       (float*)nullptr);
+  else if (P.wpc == 2)
+    hipLaunchKernelGGL((k_cells<M_STATS, 2>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
+                       (float*)nullptr);
+  else
+    hipLaunchKernelGGL((k_cells<M_STATS, 1>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
+                       (float*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, rel_tol, 0);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, rel_tol, 0, P.wpc);
   return hipGetLastError();
 }
 
@@ -757,20 +781,20 @@ hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
 }
 
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s) {
-  hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256), 0,
+  hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
                      s, P, lab, labels, (float*)nullptr);
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, 0.0, 1);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, 0.0, 1, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s) {
-  hipLaunchKernelGGL(k_cells<M_EXPORT_R>, dim3(blocks_for(P.n_cell, kCellsPerBlock)), dim3(256),
+  hipLaunchKernelGGL(k_cells<M_EXPORT_R>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256),
                      0, s, P, lab, (int32_t*)nullptr, R);
   return hipGetLastError();
 }
 
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s) {
-  hipLaunchKernelGGL(k_cells<M_EXPORT_CAND>, dim3(blocks_for(P.n_cell, kCellsPerBlock)),
+  hipLaunchKernelGGL(k_cells<M_EXPORT_CAND>, dim3(blocks_for(P.n_cell, kWavesPerBlock)),
                      dim3(256), 0, s, P, (const float*)nullptr, cand, (float*)nullptr);
   return hipGetLastError();
 }

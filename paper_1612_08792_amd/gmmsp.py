@@ -154,6 +154,60 @@ class GMMSP:
                                             c_void_p(self._stream())))
         return c
 
+    # -- schedules, autotuning and graph replay --------------------------------
+    def set_schedule(self, waves_per_cell: int):
+        check(lib().gmmsp_set_schedule(self.handle, int(waves_per_cell)))
+
+    def get_schedule(self) -> int:
+        w = c_int32()
+        check(lib().gmmsp_get_schedule(self.handle, byref(w)))
+        return w.value
+
+    def set_graph_passes(self, passes: int):
+        check(lib().gmmsp_set_graph_passes(self.handle, int(passes)))
+
+    def geometry_key(self) -> str:
+        dev = torch.cuda.get_device_name(self.device)
+        grids = ";".join(f"{W}x{H}/{g.vx}x{g.vy}" for (W, H), g in zip(self.sizes, self.grids))
+        import hashlib
+        return f"{dev}|{self.n_images}|" + hashlib.sha256(grids.encode()).hexdigest()[:16]
+
+    def autotune(self, lab: torch.Tensor, passes: int = 3, cache: str | None = "default") -> int:
+        """Pick the waves-per-cell schedule by timing it on this batch (native
+        loop in the library); results are cached by batch geometry in a JSON
+        file (~/.cache/gmmsp/schedules.json unless another path or None is
+        given).  Leaves the handle initialised by init_seeds."""
+        import json
+        import os
+        path = None
+        if cache == "default":
+            path = os.path.join(os.path.expanduser("~"), ".cache", "gmmsp", "schedules.json")
+        elif cache:
+            path = cache
+        key = self.geometry_key()
+        table = {}
+        if path and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    table = json.load(f)
+            except (OSError, ValueError):
+                table = {}
+        if key in table:
+            self.set_schedule(int(table[key]["waves_per_cell"]))
+            self.init_seeds(lab)
+            return self.get_schedule()
+        ms = np.zeros(3)
+        w = c_int32()
+        check(lib().gmmsp_autotune(self.handle, self._lab(lab), int(passes),
+                                   c_void_p(ms.ctypes.data), byref(w), c_void_p(self._stream())))
+        self.tune_ms = dict(zip((1, 2, 4), ms.tolist()))
+        if path:
+            table[key] = {"waves_per_cell": w.value, "ms": self.tune_ms}
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(table, f, indent=1)
+        return w.value
+
     def profile(self, enable: bool = True):
         check(lib().gmmsp_profile_enable(self.handle, 1 if enable else 0))
 
