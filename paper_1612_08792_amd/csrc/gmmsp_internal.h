@@ -28,8 +28,8 @@ constexpr int kMaxWpc = 4;         // largest number of waves sharing one cell
 // and f[13..15] = (mu_L, mu_a, mu_b) rounded to float32, the colour origin of
 // the statistics.  An empty slot has f[12] = -inf and zeros elsewhere.
 enum RecField {
-  R_L11 = 0, R_L12 = 1, R_L22 = 2, R_O1 = 3, R_O2 = 4, R_SL = 5, R_OL = 6,
-  R_A11 = 7, R_A12 = 8, R_A22 = 9, R_O3 = 10, R_O4 = 11, R_C = 12,
+  R_L11 = 0, R_L12 = 1, R_O1 = 2, R_O2 = 3, R_L22 = 4, R_SL = 5, R_O3 = 6, R_O4 = 7,
+  R_OL = 8, R_A11 = 9, R_A12 = 10, R_A22 = 11, R_C = 12,
   R_ML = 13, R_MA = 14, R_MB = 15
 };
 

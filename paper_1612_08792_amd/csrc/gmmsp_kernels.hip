@@ -111,12 +111,28 @@ __device__ inline void write_records(const DevPtrs& P, const ImgDesc& I, int kx,
       const int slot = 3 * (dy + 1) + (dx + 1);
       const double mxs = q.mx - (double)cx * I.vx;
       const double mys = q.my - (double)cy * I.vy;
+      float r[kRecFloats];
+      r[R_L11] = (float)l11;
+      r[R_L12] = (float)l12;
+      r[R_O1] = (float)(-(l11 * mxs + l12 * mys));
+      r[R_O2] = (float)(-l22 * mys);
+      r[R_L22] = (float)l22;
+      r[R_SL] = (float)sL;
+      r[R_O3] = (float)o3;
+      r[R_O4] = (float)o4;
+      r[R_OL] = (float)oL;
+      r[R_A11] = (float)a11;
+      r[R_A12] = (float)a12;
+      r[R_A22] = (float)a22;
+      r[R_C] = (float)c;
+      r[R_ML] = fL;
+      r[R_MA] = fa;
+      r[R_MB] = fb;
       float4* dst = reinterpret_cast<float4*>(
           P.rec + ((size_t)(I.cell_off + cy * I.ncx + cx) * kSlots + slot) * kRecFloats);
-      dst[0] = make_float4((float)l11, (float)l12, (float)l22, (float)(-(l11 * mxs + l12 * mys)));
-      dst[1] = make_float4((float)(-l22 * mys), (float)sL, (float)oL, (float)a11);
-      dst[2] = make_float4((float)a12, (float)a22, (float)o3, (float)o4);
-      dst[3] = make_float4((float)c, fL, fa, fb);
+#pragma unroll
+      for (int j = 0; j < kRecFloats / 4; ++j)
+        dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
     }
   }
 }
@@ -360,6 +376,31 @@ __device__ __forceinline__ void wave_reduce_scatter_117(float (&v)[CAP], int lan
 // e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
 // shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
 // Each record value is read once (scalar load) for all NP pixels.
+#ifndef GMMSP_MOV64
+#define GMMSP_MOV64 1
+#endif
+#ifndef GMMSP_JOINT
+#define GMMSP_JOINT 1
+#endif
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// log2 p(z; theta_k) - cmax2 with the five offsets in vector registers
+__device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2, float oL,
+                                          float o3, float o4, float xr, float yr, float L,
+                                          float A, float B) {
+  const float t1 = fmaf(f[R_L11], xr, fmaf(f[R_L12], yr, o1));
+  const float t2 = fmaf(f[R_L22], yr, o2);
+  const float w = fmaf(f[R_SL], L, oL);
+  const float u1 = fmaf(f[R_A11], A, fmaf(f[R_A12], B, o3));
+  const float u2 = fmaf(f[R_A22], B, o4);
+  float l = fmaf(-t1, t1, f[R_C]);
+  l = fmaf(-t2, t2, l);
+  l = fmaf(-w, w, l);
+  l = fmaf(-u1, u1, l);
+  l = fmaf(-u2, u2, l);
+  return l;
+}
+
 template <int NP, bool VO = false>
 __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (&xr)[NP],
                                              const float (&yr)[NP], const float (&L)[NP],
@@ -370,34 +411,70 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
   for (int p = 0; p < NP; ++p) sum[p] = 0.f;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
+    const AS4 float* f = rec + s * kRecFloats;
+#if GMMSP_MOV64
+    // An FMA reads at most one scalar register, so each offset (the addend
+    // beside a scalar record factor) must sit in a vector register: copy the
+    // offsets once per slot for all NP pixels, two at a time.
+    f2v o12 = *reinterpret_cast<const AS4 f2v*>(f + R_O1);
+    f2v o34 = *reinterpret_cast<const AS4 f2v*>(f + R_O3);
+    float oL = f[R_OL];
+    if (!VO) {
+      asm volatile("" : "+v"(o12));
+      asm volatile("" : "+v"(o34));
+      asm volatile("" : "+v"(oL));
+    }
+#endif
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const float l = VO ? eval_l_v(rec + s * kRecFloats, vo->o[s], xr[p], yr[p], L[p], A[p], B[p])
-                         : eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]);
+      float l;
+      if (VO)
+        l = eval_l_v(f, vo->o[s], xr[p], yr[p], L[p], A[p], B[p]);
+      else
+#if GMMSP_MOV64
+        l = eval_l_o(f, o12.x, o12.y, oL, o34.x, o34.y, xr[p], yr[p], L[p], A[p], B[p]);
+#else
+        l = eval_l(f, xr[p], yr[p], L[p], A[p], B[p]);
+#endif
       e[p][s] = __builtin_amdgcn_exp2f(l);
       sum[p] += e[p][s];
     }
   }
+#if GMMSP_JOINT
+  // one branch for all NP pixels, so the compiler keeps their evaluations together
+  float smin = sum[0];
+#pragma unroll
+  for (int p = 1; p < NP; ++p) smin = fminf(smin, sum[p]);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) shift[p] = 0.f;
+  if (smin < 0x1p-100f) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (sum[p] < 0x1p-100f) {
+#else
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     shift[p] = 0.f;
-    if (sum[p] < 0x1p-100f) {
-      // every candidate is far away: subtract the largest exponent first
-      float lv[kSlots];
-      float m = -INFINITY;
+    {
+      if (sum[p] < 0x1p-100f) {
+#endif
+        // every candidate is far away: subtract the largest exponent first
+        float lv[kSlots];
+        float m = -INFINITY;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        lv[s] = eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]);
-        m = fmaxf(m, lv[s]);
-      }
-      float t = 0.f;
+        for (int s = 0; s < kSlots; ++s) {
+          lv[s] = eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]);
+          m = fmaxf(m, lv[s]);
+        }
+        float t = 0.f;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        e[p][s] = __builtin_amdgcn_exp2f(lv[s] - m);
-        t += e[p][s];
+        for (int s = 0; s < kSlots; ++s) {
+          e[p][s] = __builtin_amdgcn_exp2f(lv[s] - m);
+          t += e[p][s];
+        }
+        sum[p] = t;
+        shift[p] = m;
       }
-      sum[p] = t;
-      shift[p] = m;
     }
   }
 }
