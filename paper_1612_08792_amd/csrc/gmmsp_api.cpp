@@ -73,7 +73,7 @@ int check_params(const gmmsp_params* p) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t img, state, ll_hist, cell, sp, theta, rec, part, n_done, total;
+  size_t img, state, ll_hist, cell, sp, theta, rec, part, llp, n_done, total;
   int32_t n_cell = 0, n_sp = 0;
   int64_t n_pix = 0;
 };
@@ -118,6 +118,7 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
   L->theta = o;   o = align256(o + sizeof(double) * kThetaRow * n_sp);
   L->rec = o;     o = align256(o + sizeof(float) * kRecFloats * kSlots * n_cell);
   L->part = o;    o = align256(o + sizeof(double) * kPartStride * kMaxWpc * n_cell);
+  L->llp = o;     o = align256(o + sizeof(double) * kMaxWpc * n_cell);
   L->n_done = o;  o = align256(o + sizeof(int32_t));
   L->total = o;
   L->n_cell = (int32_t)n_cell;
@@ -279,6 +280,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.theta = (double*)(base + L.theta);
   P.rec = (float*)(base + L.rec);
   P.part = (double*)(base + L.part);
+  P.llp = (double*)(base + L.llp);
   P.n_done = (int32_t*)(base + L.n_done);
   P.n_img = n_images;
   P.n_cell = L.n_cell;

@@ -83,10 +83,14 @@ __device__ inline void store_theta_row(double* row, const SpTheta& q, double mas
   row[9] = q.saa; row[10] = q.sab; row[11] = q.sbb; row[12] = mass;
 }
 
-// Write the float32 cell-slot records of superpixel (kx, ky) into the (up to)
-// nine cells whose candidate sets contain it.
-__device__ inline void write_records(const DevPtrs& P, const ImgDesc& I, int kx, int ky,
-                                     const SpTheta& q) {
+// The float32 record of superpixel (kx, ky) for the cell (kx - dx, ky - dy),
+// in which it is candidate slot 3 (dy + 1) + (dx + 1); nothing if that cell is
+// outside the grid.
+__device__ inline void write_record_slot(const DevPtrs& P, const ImgDesc& I, int kx, int ky,
+                                         const SpTheta& q, int dx, int dy) {
+  const int cx = kx - dx, cy = ky - dy;
+  if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) return;
+  const int slot = 3 * (dy + 1) + (dx + 1);
   const double s2 = sqrt(0.5 * kLog2e);  // l in log2 units: l = c - |whitened d|^2
   // spatial block: P_s = Sigma_s^-1, factored as t1^2 + t2^2
   const double l11 = s2 * sqrt(q.syy / q.det_s);
@@ -98,43 +102,38 @@ __device__ inline void write_records(const DevPtrs& P, const ImgDesc& I, int kx,
   const double a22 = s2 / sqrt(q.sbb);
   const double lndet = log(q.det_s) + log(q.sLL) + log(q.det_ab);
   const double c = kLog2e * (-2.5 * kLn2Pi - 0.5 * lndet - I.lncmax);
-  const float fL = (float)q.mL, fa = (float)q.ma, fb = (float)q.mb;
-  const double oL = -sL * q.mL;
-  const double o3 = -(a11 * q.ma + a12 * q.mb);
-  const double o4 = -a22 * q.mb;
+  // spatial offsets about the cell origin
+  const double mxs = q.mx - (double)cx * I.vx;
+  const double mys = q.my - (double)cy * I.vy;
+  float r[kRecFloats];
+  r[R_L11] = (float)l11;
+  r[R_L12] = (float)l12;
+  r[R_O1] = (float)(-(l11 * mxs + l12 * mys));
+  r[R_O2] = (float)(-l22 * mys);
+  r[R_L22] = (float)l22;
+  r[R_SL] = (float)sL;
+  r[R_O3] = (float)(-(a11 * q.ma + a12 * q.mb));
+  r[R_O4] = (float)(-a22 * q.mb);
+  r[R_OL] = (float)(-sL * q.mL);
+  r[R_A11] = (float)a11;
+  r[R_A12] = (float)a12;
+  r[R_A22] = (float)a22;
+  r[R_C] = (float)c;
+  r[R_ML] = (float)q.mL;
+  r[R_MA] = (float)q.ma;
+  r[R_MB] = (float)q.mb;
+  float4* dst = reinterpret_cast<float4*>(
+      P.rec + ((size_t)(I.cell_off + cy * I.ncx + cx) * kSlots + slot) * kRecFloats);
 #pragma unroll
-  for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int cx = kx - dx, cy = ky - dy;
-      if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) continue;
-      const int slot = 3 * (dy + 1) + (dx + 1);
-      const double mxs = q.mx - (double)cx * I.vx;
-      const double mys = q.my - (double)cy * I.vy;
-      float r[kRecFloats];
-      r[R_L11] = (float)l11;
-      r[R_L12] = (float)l12;
-      r[R_O1] = (float)(-(l11 * mxs + l12 * mys));
-      r[R_O2] = (float)(-l22 * mys);
-      r[R_L22] = (float)l22;
-      r[R_SL] = (float)sL;
-      r[R_O3] = (float)o3;
-      r[R_O4] = (float)o4;
-      r[R_OL] = (float)oL;
-      r[R_A11] = (float)a11;
-      r[R_A12] = (float)a12;
-      r[R_A22] = (float)a22;
-      r[R_C] = (float)c;
-      r[R_ML] = fL;
-      r[R_MA] = fa;
-      r[R_MB] = fb;
-      float4* dst = reinterpret_cast<float4*>(
-          P.rec + ((size_t)(I.cell_off + cy * I.ncx + cx) * kSlots + slot) * kRecFloats);
-#pragma unroll
-      for (int j = 0; j < kRecFloats / 4; ++j)
-        dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
-    }
-  }
+  for (int j = 0; j < kRecFloats / 4; ++j)
+    dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
+}
+
+// All (up to) nine records of superpixel (kx, ky), one thread.
+__device__ inline void write_records(const DevPtrs& P, const ImgDesc& I, int kx, int ky,
+                                     const SpTheta& q) {
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) write_record_slot(P, I, kx, ky, q, dx, dy);
 }
 
 __device__ inline SpTheta theta_from_row(const double* row, const ImgDesc& I) {
@@ -412,31 +411,32 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const AS4 float* f = rec + s * kRecFloats;
-#if GMMSP_MOV64
-    // An FMA reads at most one scalar register, so each offset (the addend
-    // beside a scalar record factor) must sit in a vector register: copy the
-    // offsets once per slot for all NP pixels, two at a time.
-    f2v o12 = *reinterpret_cast<const AS4 f2v*>(f + R_O1);
-    f2v o34 = *reinterpret_cast<const AS4 f2v*>(f + R_O3);
-    float oL = f[R_OL];
-    if (!VO) {
+    float l[NP];
+    if constexpr (VO) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) l[p] = eval_l_v(f, vo->o[s], xr[p], yr[p], L[p], A[p], B[p]);
+    } else if constexpr (GMMSP_MOV64 && NP > 1) {
+      // An FMA reads at most one scalar register, so each offset (the addend
+      // beside a scalar record factor) must sit in a vector register: copy
+      // the offsets once per slot for all NP pixels, two at a time.  (With
+      // one pixel per lane the records are loop invariant and the compiler
+      // keeps the offsets in vector registers by itself.)
+      f2v o12 = *reinterpret_cast<const AS4 f2v*>(f + R_O1);
+      f2v o34 = *reinterpret_cast<const AS4 f2v*>(f + R_O3);
+      float oL = f[R_OL];
       asm volatile("" : "+v"(o12));
       asm volatile("" : "+v"(o34));
       asm volatile("" : "+v"(oL));
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        l[p] = eval_l_o(f, o12.x, o12.y, oL, o34.x, o34.y, xr[p], yr[p], L[p], A[p], B[p]);
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) l[p] = eval_l(f, xr[p], yr[p], L[p], A[p], B[p]);
     }
-#endif
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      float l;
-      if (VO)
-        l = eval_l_v(f, vo->o[s], xr[p], yr[p], L[p], A[p], B[p]);
-      else
-#if GMMSP_MOV64
-        l = eval_l_o(f, o12.x, o12.y, oL, o34.x, o34.y, xr[p], yr[p], L[p], A[p], B[p]);
-#else
-        l = eval_l(f, xr[p], yr[p], L[p], A[p], B[p]);
-#endif
-      e[p][s] = __builtin_amdgcn_exp2f(l);
+      e[p][s] = __builtin_amdgcn_exp2f(l[p]);
       sum[p] += e[p][s];
     }
   }
@@ -684,30 +684,35 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
     // each wave of a cell adds its own pixels' share; the constant term once
     const double cst = sub == 0 ? (double)npix * Ip->lncmax : 0.0;
-    if (lane == 0) P.part[((size_t)sub * P.n_cell + cell) * kPartStride + kLLSlot] = kLn2 * ll + cst;
+    if (lane == 0) P.llp[(size_t)sub * P.n_cell + cell] = kLn2 * ll + cst;
   }
 }
 
 // ---------------------------------------------------------------------------
 // L(theta^t) per image and the stop rule; one block per image
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
-                                                   int nsub) {
-  __shared__ double red[256];
+constexpr int kLLThreads = 1024;
+
+__global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
+                                                          int nsub) {
+  __shared__ double red[kLLThreads];
   const int b = blockIdx.x;
   const ImgDesc* I = P.img + b;
   ImgState* st = P.state + b;
   const int done = st->done;
   if (!final_pass && done) return;
   const int ncells = I->ncells;
+  // fixed order: thread i sums cells i, i + 1024, ... of every cell wave, then
+  // a fixed tree; consecutive threads read consecutive cells
   double s = 0.0;
-  for (int c = threadIdx.x; c < ncells; c += 256)
-    for (int u = 0; u < nsub; ++u)
-      s += P.part[((size_t)u * P.n_cell + I->cell_off + c) * kPartStride + kLLSlot];
+  for (int u = 0; u < nsub; ++u) {
+    const double* llp = P.llp + (size_t)u * P.n_cell + I->cell_off;
+    for (int c = threadIdx.x; c < ncells; c += kLLThreads) s += llp[c];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
 #pragma unroll
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = kLLThreads / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -848,7 +853,7 @@ hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s)
 }
 
 hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, rel_tol, 0, P.wpc);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, rel_tol, 0, P.wpc);
   return hipGetLastError();
 }
 
@@ -860,7 +865,7 @@ hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s) {
   hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
                      s, P, lab, labels, (float*)nullptr);
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(256), 0, s, P, 0.0, 1, 1);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, 1, 1);
   return hipGetLastError();
 }
 
