@@ -254,7 +254,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"batched 4K plain EM to convergence: {len(ims)} x 3840x2160 "
+            "workload": f"batched 4K EM to convergence, learned warm start vs plain grid seeds: {len(ims)} x 3840x2160 "
                         f"Voronoi-Lab (2000 regions, sigma~U[1,6]), K={K_req} requested "
                         f"({m.grids[0].K} on the grid), rel-tol {args.tol:g}, cap {args.cap}",
             "images": len(ims),
