@@ -260,6 +260,42 @@ int gmmsp_ws_train_step(gmmsp_handle* h, float* params_dev, float* m_dev, float*
 int gmmsp_ws_read(gmmsp_handle* h, int32_t which, void* host, size_t bytes, void* stream);
 int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Connectivity post-processing (Algorithm 1, last step; the paragraph on
+ * enforcing connectivity in Sec. III-C).
+ *
+ * The labelled superpixels may be disconnected.  Segments are the
+ * 4-connected components of equal label in each image of the batch; a
+ * segment's id is the raster index y W + x (inside its image) of its first
+ * pixel.  Segments smaller than a quarter of the desired superpixel size
+ * (4 size < v_x v_y of the image's grid) are visited in ascending order of
+ * their size (ties: ascending id) and each one still small when visited is
+ * merged into the neighbouring segment (as merged so far) whose mean Lab
+ * colour is closest: squared Euclidean distance in FP64 between the
+ * segments' own mean colours, each the mean of the pixels' colours
+ * quantised to multiples of 2^-20, ties to the smaller id; the destination's
+ * size grows by the merged size.  The neighbours of a segment are those
+ * holding a 4-neighbour of any pixel merged into it so far.  A segment with
+ * no neighbour stays.  The result is a partition into connected segments.
+ *
+ * gmmsp_conn_workspace_bytes: size of the caller-allocated device workspace
+ *   (256-byte aligned), about 88 bytes per pixel of the batch (the worst case
+ *   of one segment per pixel).
+ * gmmsp_connectivity: labels_dev (int32 per pixel of the batch, any values:
+ *   only equality matters, e.g. the output of gmmsp_label) and lab_dev (the
+ *   batch's Lab pixels) in; out_dev (int32 per pixel) receives the id of the
+ *   segment the pixel ends in.  Needs the handle's geometry only (no
+ *   initialisation).  counts_host (nullable, 4 int32 per image): segments,
+ *   small segments, merged segments, final segments.  Synchronises `stream`
+ *   (the segment count is read back between two groups of launches).
+ *   Errors: E_INVAL for null or misaligned pointers, E_SIZE for a short
+ *   workspace or a batch of 2^31 - 1 pixels or more.
+ * ------------------------------------------------------------------------ */
+int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes);
+int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t* counts_host,
+                       void* stream);
+
 const char* gmmsp_last_error(void);
 
 #ifdef __cplusplus

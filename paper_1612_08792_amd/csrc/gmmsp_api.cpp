@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -920,6 +921,86 @@ int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t byte
   hipError_t e = hipMemcpyAsync(h->ws.ptrs[which], host, bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_write");
+  return GMMSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Connectivity post-processing
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct ConnSizes {
+  size_t pix, bsum, counts, seg, colsum, total;
+};
+
+ConnSizes conn_sizes(const gmmsp_handle* h) {
+  ConnSizes z;
+  const size_t n = (size_t)h->n_pix;
+  z.pix = align256(sizeof(int) * n);
+  z.bsum = align256(sizeof(int) * (gmmsp::conn_scan_blocks((int64_t)n) + 1));
+  z.counts = align256(sizeof(int) * (4 * (size_t)h->n_img + 1));
+  z.seg = z.pix;  // at most one segment per pixel
+  z.colsum = align256(sizeof(unsigned long long) * 3 * n);
+  z.total = 3 * z.pix + z.bsum + z.counts + 13 * z.seg + z.colsum;
+  return z;
+}
+
+}  // namespace
+
+int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
+  if (!h || !bytes) return fail(GMMSP_E_INVAL, "null pointer");
+  *bytes = conn_sizes(h).total;
+  return GMMSP_OK;
+}
+
+int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t* counts_host,
+                       void* stream) {
+  if (!h || !lab_dev || !labels_dev || !out_dev || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
+  if (h->n_pix >= ((int64_t)1 << 31) - 1)
+    return fail(GMMSP_E_SIZE, "connectivity needs fewer than 2^31 - 1 pixels per batch");
+  const ConnSizes z = conn_sizes(h);
+  if (ws_bytes < z.total) return fail(GMMSP_E_SIZE, "connectivity workspace %zu < %zu bytes", ws_bytes, z.total);
+  char* b = (char*)ws_dev;
+  size_t t = 0;
+  auto take = [&](size_t n) { void* p = b + t; t += n; return p; };
+  ConnPtrs C;
+  C.n_pix = h->n_pix;
+  C.par = (int*)take(z.pix);
+  C.segid = (int*)take(z.pix);
+  C.scan = (int*)take(z.pix);
+  C.bsum = (int*)take(z.bsum);
+  C.counts = (int*)take(z.counts);
+  C.total = C.counts + 4 * h->n_img;
+  int** seg[13] = {&C.seg_root, &C.seg_img, &C.size0, &C.size, &C.ccnt, &C.coff, &C.cursor,
+                   &C.list, &C.poff, &C.cpar, &C.mpar, &C.next, &C.tail};
+  for (int i = 0; i < 13; ++i) *seg[i] = (int*)take(z.seg);
+  C.colsum = (unsigned long long*)take(z.colsum);
+  int max_pix = 0;
+  for (const ImgDesc& I : h->img) max_pix = std::max(max_pix, I.W * I.H);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = conn_launch_components(C, h->P.img, h->n_img, max_pix, labels_dev, s);
+  int n_seg = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&n_seg, C.total, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity (components)");
+  if (n_seg < 1 || n_seg > h->n_pix) return fail(GMMSP_E_STATE, "segment count %d out of range", n_seg);
+  e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, n_seg, lab_dev, out_dev, s);
+  if (e == hipSuccess && counts_host) {
+    std::vector<int> c(4 * (size_t)h->n_img);
+    e = hipMemcpyAsync(c.data(), C.counts, sizeof(int) * c.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+      for (int32_t i = 0; i < h->n_img; ++i) {
+        counts_host[4 * i + 0] = c[4 * i + 0];
+        counts_host[4 * i + 1] = c[4 * i + 1];
+        counts_host[4 * i + 2] = c[4 * i + 2];
+        counts_host[4 * i + 3] = c[4 * i + 0] - c[4 * i + 2];
+      }
+  }
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity");
   return GMMSP_OK;
 }
 

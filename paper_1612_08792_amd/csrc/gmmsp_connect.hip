@@ -1,0 +1,511 @@
+// Connectivity post-processing (Algorithm 1, last step; the paragraph on
+// enforcing connectivity in Sec. III-C) for a batch of label maps on gfx950.
+//
+// The paper sorts the isolated pieces of the superpixels by size, ascending,
+// and merges each piece smaller than a quarter of the desired superpixel size,
+// in that order, into the neighbouring superpixel closest in colour; a merged
+// piece's size becomes zero and its destination's size grows by it.
+//
+// Definitions (pieces are "segments"):
+//   * a segment is a 4-connected component of equal label; its id is the
+//     raster index of its first pixel; small means 4 size < v_x v_y;
+//   * colours are the segments' own mean Lab colours, fixed for the whole
+//     procedure, from integer sums of the pixel colours quantised to 2^-20;
+//   * the neighbours of a segment are the current segments holding a
+//     4-neighbour of any pixel merged into it so far; the destination is the
+//     one at the smallest squared colour distance (FP64, no fused
+//     multiply-add), ties to the smallest id.
+//
+// Parallel form of the sequential procedure.  A small segment's decision
+// reads only (a) its own size and pixels, which change only when small
+// segments adjacent to it are merged into it, and (b) the current owner of
+// each neighbouring pixel, which changes only for neighbouring small
+// segments.  So the clusters of small segments joined by adjacency never
+// influence each other: each cluster runs the procedure sequentially, in the
+// global order restricted to it, on one thread, and all clusters run in
+// parallel.  Merges into a large segment from several clusters only add to
+// its size, which no decision reads (a large segment is never merged).
+//
+// Steps: pixel union-find of equal-label 4-neighbours (roots are the minimum
+// index, so the partition and ids are unique whatever the order of the
+// atomics); compaction of the roots to segment indices (in id order); sizes
+// and integer colour sums with integer atomics (exact); cluster union-find
+// over adjacent small segments; per-cluster lists sorted by (size, id) with
+// a heap sort; per-source pixel lists; the sequential merge per cluster; the
+// output ids.
+#include "gmmsp_internal.h"
+
+#include <math.h>
+
+namespace gmmsp {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kScanBlock = 1024;  // elements per block of the scan (4 per thread)
+
+__device__ __forceinline__ int ld_acq(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// root of x in a forest with parent[x] <= x (every link points to a smaller
+// index, so the walk strictly decreases and ends)
+__device__ int uf_find(int* par, int x) {
+  int y = ld_acq(par + x);
+  while (y != x) {
+    x = y;
+    y = ld_acq(par + x);
+  }
+  return x;
+}
+
+// join the sets of a and b by hanging the larger root under the smaller; a
+// failed compare-and-swap returns the newer, strictly smaller parent, so the
+// loop ends
+__device__ void uf_unite(int* par, int a, int b) {
+  a = uf_find(par, a);
+  b = uf_find(par, b);
+  while (a != b) {
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicCAS(par + a, a, b);
+    if (old == a) return;
+    a = uf_find(par, old);
+    b = uf_find(par, b);
+  }
+}
+
+__device__ __forceinline__ bool img_pixel(const ImgDesc* img, int& b, int& j, int& W, int& H,
+                                          int64_t& off) {
+  b = blockIdx.y;
+  const ImgDesc I = img[b];
+  W = I.W;
+  H = I.H;
+  off = I.pix_off;
+  j = blockIdx.x * kT + threadIdx.x;
+  return j < W * H;
+}
+
+__device__ __forceinline__ bool is_small(const ImgDesc* img, const int* seg_img,
+                                         const int* size0, int s) {
+  const ImgDesc& I = img[seg_img[s]];
+  return 4LL * size0[s] < (int64_t)I.vx * I.vy;
+}
+
+__device__ double colour_dist2(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  const double dL = a[0] - b[0];
+  const double da = a[1] - b[1];
+  const double db = a[2] - b[2];
+  return (dL * dL + da * da) + db * db;
+}
+
+// merge parent walk: a segment points to the segment it was merged into
+__device__ __forceinline__ int m_find(const int* mpar, int t) {
+  int u = mpar[t];
+  while (u != t) {
+    t = u;
+    u = mpar[t];
+  }
+  return t;
+}
+
+// ---- pixel components ------------------------------------------------------
+
+__global__ __launch_bounds__(kT) void k_cc_init(const ImgDesc* img, int* par) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  par[i] = i;
+}
+
+__global__ __launch_bounds__(kT) void k_cc_link(const ImgDesc* img, const int32_t* labels,
+                                                int* par) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int x = j % W, y = j / W;
+  const int32_t l = labels[i];
+  if (x > 0 && labels[i - 1] == l) uf_unite(par, i, i - 1);
+  if (y > 0 && labels[i - W] == l) uf_unite(par, i, i - W);
+}
+
+__global__ __launch_bounds__(kT) void k_cc_flatten(const ImgDesc* img, int* par, int* flag) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int r = uf_find(par, i);
+  par[i] = r;
+  flag[i] = r == i;
+}
+
+// ---- exclusive scan of int32 (in place), total to *total ---------------------
+
+__global__ __launch_bounds__(kT) void k_scan_blocks(int* a, int n, int* bsum) {
+  __shared__ int sh[kT];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int v[4];
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = base + k < n ? a[base + k] : 0;
+    t += v[k];
+  }
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread totals
+  for (int o = 1; o < kT; o <<= 1) {
+    const int u = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += u;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - t;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) a[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kT - 1) bsum[blockIdx.x] = sh[kT - 1];
+}
+
+// one block: exclusive scan of the nb block totals, in chunks of kT
+__global__ __launch_bounds__(kT) void k_scan_totals(int* bsum, int nb, int* total) {
+  __shared__ int sh[kT];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += kT) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kT; o <<= 1) {
+      const int u = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += sh[kT - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_add(int* a, int n, const int* bsum) {
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  const int add = bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + k < n) a[base + k] += add;
+}
+
+// ---- segments ---------------------------------------------------------------
+
+__global__ __launch_bounds__(kT) void k_seg_assign(const ImgDesc* img, const int* par,
+                                                   const int* scan, int* segid, int* seg_root,
+                                                   int* seg_img) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int r = par[i];
+  const int s = scan[r];
+  segid[i] = s;
+  if (r == i) {
+    seg_root[s] = i;
+    seg_img[s] = b;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_seg_zero(int n_seg, int* size0,
+                                                 unsigned long long* colsum, int* ccnt) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  size0[s] = 0;
+  colsum[3 * s] = 0ull;
+  colsum[3 * s + 1] = 0ull;
+  colsum[3 * s + 2] = 0ull;
+  ccnt[s] = 0;
+}
+
+// size and integer colour sums: exact, so the atomics' order does not matter
+__global__ __launch_bounds__(kT) void k_seg_stats(const ImgDesc* img, const float* lab,
+                                                  const int* segid, int* size0,
+                                                  unsigned long long* colsum) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int s = segid[i];
+  atomicAdd(size0 + s, 1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long q = (long long)rint((double)lab[3 * (int64_t)i + c] * 1048576.0);
+    atomicAdd(colsum + 3 * s + c, (unsigned long long)q);
+  }
+}
+
+// means (in place of the sums), working sizes, parents, chains
+__global__ __launch_bounds__(kT) void k_seg_prep(int n_seg, const int* size0,
+                                                 unsigned long long* colsum, int* size,
+                                                 int* mpar, int* cpar, int* next, int* tail) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const int n = size0[s];
+  double* mean = reinterpret_cast<double*>(colsum + 3 * s);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long q = (long long)colsum[3 * s + c];
+    mean[c] = (double)q / (double)n * 0x1p-20;
+  }
+  size[s] = n;
+  mpar[s] = s;
+  cpar[s] = s;
+  next[s] = -1;
+  tail[s] = s;
+}
+
+// clusters: union of 4-adjacent small segments
+__global__ __launch_bounds__(kT) void k_cl_link(const ImgDesc* img, const int* segid,
+                                                const int* seg_img, const int* size0,
+                                                int* cpar) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int s = segid[i];
+  if (!is_small(img, seg_img, size0, s)) return;
+  const int x = j % W, y = j / W;
+  if (x > 0) {
+    const int t = segid[i - 1];
+    if (t != s && is_small(img, seg_img, size0, t)) uf_unite(cpar, s, t);
+  }
+  if (y > 0) {
+    const int t = segid[i - W];
+    if (t != s && is_small(img, seg_img, size0, t)) uf_unite(cpar, s, t);
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_cl_count(const ImgDesc* img, int n_seg,
+                                                 const int* seg_img, const int* size0, int* cpar,
+                                                 int* ccnt) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg || !is_small(img, seg_img, size0, s)) return;
+  const int r = uf_find(cpar, s);
+  cpar[s] = r;
+  atomicAdd(ccnt + r, 1);
+}
+
+// cluster lists (any order) and the sources' pixel-list sizes
+__global__ __launch_bounds__(kT) void k_cl_fill(const ImgDesc* img, int n_seg, const int* seg_img,
+                                                const int* size0, const int* cpar,
+                                                const int* coff, int* cursor, int* list,
+                                                int* psz) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const bool small = is_small(img, seg_img, size0, s);
+  psz[s] = small ? size0[s] : 0;
+  if (!small) return;
+  const int r = cpar[s];
+  const int pos = atomicAdd(cursor + r, 1);
+  list[coff[r] + pos] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_zero(int n, int* a) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+__global__ __launch_bounds__(kT) void k_px_fill(const ImgDesc* img, const int* segid,
+                                                const int* seg_img, const int* size0,
+                                                const int* poff, int* cursor, int* plist) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  const int s = segid[i];
+  if (!is_small(img, seg_img, size0, s)) return;
+  plist[poff[s] + atomicAdd(cursor + s, 1)] = i;
+}
+
+__device__ __forceinline__ bool key_less(const int* size0, int a, int b) {
+  return size0[a] < size0[b] || (size0[a] == size0[b] && a < b);
+}
+
+__device__ void sift_down(int* v, const int* size0, int root, int n) {
+  while (true) {
+    int c = 2 * root + 1;
+    if (c >= n) return;
+    if (c + 1 < n && key_less(size0, v[c], v[c + 1])) ++c;
+    if (!key_less(size0, v[root], v[c])) return;
+    const int t = v[root];
+    v[root] = v[c];
+    v[c] = t;
+    root = c;
+  }
+}
+
+// The merge, one thread per cluster: sort its sources by (size, id), then
+// visit them in that order.
+__global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, const int* seg_img,
+                                              const int* seg_root, const int* size0,
+                                              const int* cpar, const int* ccnt, const int* coff,
+                                              int* list, const int* poff, const int* plist,
+                                              const int* segid, const double* mean, int* size,
+                                              int* mpar, int* next, int* tail) {
+  const int r = blockIdx.x * kT + threadIdx.x;
+  if (r >= n_seg || !is_small(img, seg_img, size0, r) || cpar[r] != r) return;
+  const int n = ccnt[r];
+  int* v = list + coff[r];
+  // heap sort, ascending by (size, id)
+  for (int k = n / 2 - 1; k >= 0; --k) sift_down(v, size0, k, n);
+  for (int e = n - 1; e > 0; --e) {
+    const int t = v[0];
+    v[0] = v[e];
+    v[e] = t;
+    sift_down(v, size0, 0, e);
+  }
+  const ImgDesc& I = img[seg_img[r]];
+  const int W = I.W, H = I.H;
+  const int off = (int)I.pix_off;
+  const int64_t desired = (int64_t)I.vx * I.vy;
+  for (int q = 0; q < n; ++q) {
+    const int s = v[q];
+    if (4LL * size[s] >= desired) continue;
+    const double* ms = mean + 3 * (int64_t)s;
+    int best = -1;
+    double bd = 0.0;
+    for (int m = s; m >= 0; m = next[m]) {
+      const int p0 = poff[m], np = size0[m];
+      for (int u = 0; u < np; ++u) {
+        const int j = plist[p0 + u] - off;
+        const int x = j % W, y = j / W;
+        int nb[4];
+        int k = 0;
+        if (y > 0) nb[k++] = j - W;
+        if (y + 1 < H) nb[k++] = j + W;
+        if (x > 0) nb[k++] = j - 1;
+        if (x + 1 < W) nb[k++] = j + 1;
+        for (int e = 0; e < k; ++e) {
+          const int t = m_find(mpar, segid[off + nb[e]]);
+          if (t == s) continue;
+          const double d = colour_dist2(ms, mean + 3 * (int64_t)t);
+          if (best < 0 || d < bd || (d == bd && t < best)) {
+            best = t;
+            bd = d;
+          }
+        }
+      }
+    }
+    if (best < 0) continue;
+    mpar[s] = best;
+    atomicAdd(size + best, size[s]);
+    size[s] = 0;
+    if (is_small(img, seg_img, size0, best)) {  // same cluster: hand over the pixels
+      next[tail[best]] = s;
+      tail[best] = tail[s];
+    }
+  }
+  (void)seg_root;
+}
+
+__global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* segid, int* mpar,
+                                              const int* seg_root, int32_t* out) {
+  int b, j, W, H;
+  int64_t off;
+  if (!img_pixel(img, b, j, W, H, off)) return;
+  const int i = (int)(off + j);
+  int t = segid[i];
+  // walk to the final segment, halving the path (every write is an ancestor)
+  int u = mpar[t];
+  while (u != t) {
+    const int w = mpar[u];
+    mpar[t] = w;
+    t = u;
+    u = w;
+  }
+  out[i] = (int32_t)(seg_root[t] - off);
+}
+
+__global__ __launch_bounds__(kT) void k_counts(const ImgDesc* img, int n_seg, const int* seg_img,
+                                               const int* size0, const int* mpar, int* counts) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  int* c = counts + 4 * seg_img[s];
+  atomicAdd(c + 0, 1);
+  if (is_small(img, seg_img, size0, s)) atomicAdd(c + 1, 1);
+  if (mpar[s] != s) atomicAdd(c + 2, 1);
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+hipError_t scan(int* a, int n, int* bsum, int* total, hipStream_t s) {
+  const int nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 0) hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kT), 0, s, a, n, bsum);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kT), 0, s, bsum, nb, total);
+  if (nb > 0) hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kT), 0, s, a, n, bsum);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t conn_scan_blocks(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock); }
+
+hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
+                                  int max_pixels, const int32_t* labels, hipStream_t s) {
+  const dim3 g(blocks(max_pixels), n_img);
+  hipLaunchKernelGGL(k_cc_init, g, dim3(kT), 0, s, img, C.par);
+  hipLaunchKernelGGL(k_cc_link, g, dim3(kT), 0, s, img, labels, C.par);
+  hipLaunchKernelGGL(k_cc_flatten, g, dim3(kT), 0, s, img, C.par, C.scan);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return scan(C.scan, (int)C.n_pix, C.bsum, C.total, s);
+}
+
+hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
+                             int n_seg, const float* lab, int32_t* out, hipStream_t s) {
+  const dim3 g(blocks(max_pixels), n_img);
+  const unsigned gs = blocks(n_seg);
+  hipLaunchKernelGGL(k_seg_assign, g, dim3(kT), 0, s, img, C.par, C.scan, C.segid, C.seg_root,
+                     C.seg_img);
+  hipLaunchKernelGGL(k_seg_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.size0, C.colsum, C.ccnt);
+  hipLaunchKernelGGL(k_seg_stats, g, dim3(kT), 0, s, img, lab, C.segid, C.size0, C.colsum);
+  hipLaunchKernelGGL(k_seg_prep, dim3(gs), dim3(kT), 0, s, n_seg, C.size0, C.colsum, C.size,
+                     C.mpar, C.cpar, C.next, C.tail);
+  hipLaunchKernelGGL(k_cl_link, g, dim3(kT), 0, s, img, C.segid, C.seg_img, C.size0, C.cpar);
+  hipLaunchKernelGGL(k_cl_count, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0,
+                     C.cpar, C.ccnt);
+  hipError_t e = hipMemcpyAsync(C.coff, C.ccnt, sizeof(int) * (size_t)n_seg,
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  e = scan(C.coff, n_seg, C.bsum, C.total, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.cursor);
+  hipLaunchKernelGGL(k_cl_fill, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.cpar,
+                     C.coff, C.cursor, C.list, C.poff);
+  e = scan(C.poff, n_seg, C.bsum, C.total, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.cursor);
+  // the pixel union-find array is free now: it holds the sources' pixel lists
+  hipLaunchKernelGGL(k_px_fill, g, dim3(kT), 0, s, img, C.segid, C.seg_img, C.size0, C.poff,
+                     C.cursor, C.par);
+  hipLaunchKernelGGL(k_merge, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.seg_root,
+                     C.size0, C.cpar, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
+                     reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail);
+  hipLaunchKernelGGL(k_final, g, dim3(kT), 0, s, img, C.segid, C.mpar, C.seg_root, out);
+  hipLaunchKernelGGL(k_zero, dim3(blocks(4 * n_img)), dim3(kT), 0, s, 4 * n_img, C.counts);
+  hipLaunchKernelGGL(k_counts, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.mpar,
+                     C.counts);
+  return hipGetLastError();
+}
+
+}  // namespace gmmsp

@@ -20,12 +20,14 @@ constexpr int kMaxWpc = 4;         // largest number of waves sharing one cell
 // Cell-slot record: the parameters of the superpixel in slot s of cell c, in
 // float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
 // relative to the cell origin with colour (L, a, b):
-//   t1 = f[0] xr + f[1] yr + f[3],  t2 = f[2] yr + f[4],
-//   w  = f[5] L + f[6],
-//   u1 = f[7] a + f[8] b + f[10],   u2 = f[9] b + f[11],
-//   l  = f[12] - t1^2 - t2^2 - w^2 - u1^2 - u2^2 = log2 p(z; theta_k) - cmax2
-// and f[13..15] = (mu_L, mu_a, mu_b) rounded to float32, the colour origin of
-// the statistics.  An empty slot has f[12] = -inf and zeros elsewhere.
+//   t1 = L11 xr + L12 yr + O1,  t2 = L22 yr + O2,
+//   w  = SL L + OL,
+//   u1 = A11 a + A12 b + O3,    u2 = A22 b + O4,
+//   l  = C - t1^2 - t2^2 - w^2 - u1^2 - u2^2 = log2 p(z; theta_k) - cmax2
+// and (ML, MA, MB) = (mu_L, mu_a, mu_b) rounded to float32, the colour origin
+// of the statistics.  The offset pairs (O1, O2) and (O3, O4) sit at 8-byte
+// aligned positions so that each pair moves to vector registers in one 64-bit
+// move.  An empty slot has C = -inf and zeros elsewhere.
 enum RecField {
   R_L11 = 0, R_L12 = 1, R_O1 = 2, R_O2 = 3, R_L22 = 4, R_SL = 5, R_O3 = 6, R_O4 = 7,
   R_OL = 8, R_A11 = 9, R_A12 = 10, R_A22 = 11, R_C = 12,
@@ -111,5 +113,26 @@ hipError_t ws_launch_adam(float* w, float* m, float* v, const float* grad, int n
 hipError_t ws_launch_apply(const DevPtrs& P, const float* lab, const float* out, uint32_t mask,
                            double* rows, hipStream_t s);
 hipError_t ws_launch_targets(const DevPtrs& P, const float* lab, float* tgt, hipStream_t s);
+
+// Connectivity post-processing (gmmsp_connect.hip).  Per-pixel arrays hold
+// n_pix entries; per-segment arrays hold n_pix entries (a segment has at least
+// one pixel).
+struct ConnPtrs {
+  int64_t n_pix;
+  int* par;                 // pixel union-find, then the small segments' pixel lists
+  int* segid;               // segment index of each pixel (segments in id order)
+  int* scan;                // root flags, then their exclusive scan
+  int* bsum;                // scan block totals
+  int* total;               // scan total (the number of segments after the first scan)
+  int* counts;              // [n_img][4]: segments, small, merged, (unused)
+  int *seg_root, *seg_img, *size0, *size, *ccnt, *coff, *cursor, *list, *poff;
+  int *cpar, *mpar, *next, *tail;
+  unsigned long long* colsum;  // [n_seg][3] quantised colour sums, then FP64 means
+};
+size_t conn_scan_blocks(int64_t n);
+hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
+                                  int max_pixels, const int32_t* labels, hipStream_t s);
+hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
+                             int n_seg, const float* lab, int32_t* out, hipStream_t s);
 
 }  // namespace gmmsp

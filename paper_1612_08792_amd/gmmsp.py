@@ -284,6 +284,29 @@ class GMMSP:
         check(lib().gmmsp_ws_write(self.handle, idx, c_void_p(a.ctypes.data), a.nbytes,
                                    c_void_p(self._stream())))
 
+    # -- connectivity post-processing (Algorithm 1, last step) ----------------
+    def connectivity(self, lab: torch.Tensor, labels: torch.Tensor,
+                     out: torch.Tensor | None = None):
+        """Merge the small disconnected segments of `labels` (int32 per pixel of
+        the batch) into colour-nearest neighbours.  Returns (out, counts): out
+        holds, per pixel, the image-local raster index of its final segment's
+        first pixel; counts (n_images, 4): segments, small, merged, final."""
+        if labels.dtype != torch.int32 or not labels.is_contiguous() or \
+                labels.numel() != self.n_pixels or labels.device != self.device:
+            raise ValueError("labels must be a contiguous int32 tensor of n_pixels on the handle's device")
+        if out is None:
+            out = torch.empty_like(labels)
+        nbytes = c_size_t(0)
+        check(lib().gmmsp_conn_workspace_bytes(self.handle, byref(nbytes)))
+        ws = getattr(self, "conn_workspace", None)
+        if ws is None or ws.numel() < nbytes.value:
+            ws = self.conn_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        counts = np.zeros((self.n_images, 4), dtype=np.int32)
+        check(lib().gmmsp_connectivity(self.handle, self._lab(lab), c_void_p(_ptr(labels)),
+                                       c_void_p(_ptr(out)), c_void_p(_ptr(ws)), nbytes.value,
+                                       c_void_p(counts.ctypes.data), c_void_p(self._stream())))
+        return out, counts
+
     # -- helpers -------------------------------------------------------------
     def image_slice(self, b: int) -> slice:
         return slice(int(self.pix_off[b]), int(self.pix_off[b + 1]))

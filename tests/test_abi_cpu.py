@@ -113,3 +113,10 @@ def test_create_rejects_bad_arguments_before_any_device_work():
     assert L.gmmsp_em_iterate(None, None, 1, 0.0, None, None) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_label(None, None, None, None, None) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_init_seeds(None, None, None) == _lib.GMMSP_E_INVAL
+
+
+def test_connectivity_rejects_bad_arguments_before_any_device_work():
+    L = _lib.lib()
+    p = c_void_p(0x1000)
+    assert L.gmmsp_conn_workspace_bytes(None, byref(c_size_t(0))) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_connectivity(None, p, p, p, p, 1 << 20, None, None) == _lib.GMMSP_E_INVAL

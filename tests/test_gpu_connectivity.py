@@ -1,0 +1,151 @@
+"""GPU connectivity post-processing (Algorithm 1, last step) through the C ABI
+against the CPU oracle: bit-exact output ids and counts on the oracle EM's
+labels, on fragment-heavy and checkerboard label maps, on hand-built cases, in
+uneven batches; at 4K, the properties that hold at any size."""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+import synth
+from oracle import conn_oracle as C
+from oracle import gmm_oracle as O
+from paper_1612_08792_amd.gmmsp import GMMSP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def run_gpu(dev, items, v):
+    """items: list of (labels (H, W) ints, lab (H, W, 3) float32); grid spacing v."""
+    sizes = [(l.shape[1], l.shape[0]) for l, _ in items]
+    m = GMMSP(sizes, v=v, device=dev)
+    labels = torch.from_numpy(np.concatenate([l.astype(np.int32).ravel() for l, _ in items])).to(dev)
+    lab = torch.from_numpy(np.concatenate([x.astype(np.float32).reshape(-1) for _, x in items])).to(dev)
+    out, counts = m.connectivity(lab, labels)
+    out = out.cpu().numpy()
+    res = [out[m.image_slice(b)].reshape(items[b][0].shape) for b in range(len(items))]
+    return res, counts, m
+
+
+def check_exact(dev, items, v):
+    got, counts, _ = run_gpu(dev, items, v)
+    for b, (labels, lab) in enumerate(items):
+        want, info = C.enforce_connectivity(labels, lab, v, v)
+        assert np.array_equal(got[b], want), b
+        assert list(counts[b]) == [info["segments"], info["small"], info["merged"], info["final"]], b
+    return counts
+
+
+def fragmented(seed, H, W, v, p=0.15):
+    rng = np.random.default_rng(seed)
+    labels = (np.arange(H)[:, None] // v) * 1000 + (np.arange(W)[None, :] // v)
+    flip = rng.random((H, W)) < p
+    labels = np.where(flip, labels + rng.integers(-1, 2, (H, W)), labels)
+    lab = rng.normal(50, 12, (H, W, 3)).astype(np.float32)
+    return labels, lab
+
+
+def test_oracle_em_labels_481x321(dev):
+    im = synth.config1_image()
+    g = O.make_grid(im.W, im.H, K=im.K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=10)
+    labels = ref["labels"].reshape(im.H, im.W)
+    counts = check_exact(dev, [(labels, im.lab.numpy())], g.vx)
+    say("481x321 after T = 10: segments, small, merged, final =", list(counts[0]))
+
+
+def test_fragmented_uneven_batch(dev):
+    items = [fragmented(10, 97, 131, 9), fragmented(11, 40, 27, 9, 0.3), fragmented(12, 9, 9, 9, 0.5)]
+    check_exact(dev, items, 9)
+
+
+def test_checkerboard_is_one_cluster(dev):
+    # every pixel is its own segment, all small, all in one cluster
+    H, W = 40, 48
+    labels = (np.arange(H)[:, None] + np.arange(W)[None, :]) % 2
+    rng = np.random.default_rng(13)
+    lab = rng.uniform(0, 100, (H, W, 3)).astype(np.float32)
+    counts = check_exact(dev, [(labels, lab)], 8)
+    assert counts[0][0] == H * W
+
+
+def test_hand_cases(dev):
+    # inherited neighbours: A joins B, B then joins Y through A's pixel
+    labels = np.zeros((10, 10), np.int64)
+    lab = np.zeros((10, 10, 3), np.float32)
+    lab[..., 0] = 10.0
+    labels[0, :] = 3
+    lab[0, :, 0] = 51.0
+    labels[1, 0] = 1
+    lab[1, 0, 0] = 50.0
+    labels[2:4, 0:3] = 2
+    lab[2:4, 0:3, 0] = 50.2
+    # equal distances: the smaller id wins
+    l2 = np.zeros((8, 8), np.int64)
+    l2[:, 4:] = 1
+    l2[3, 3] = 2
+    x2 = np.zeros((8, 8, 3), np.float32)
+    x2[..., 0] = 40.0
+    x2[:, 4:, 0] = 60.0
+    x2[3, 3, 0] = 50.0
+    check_exact(dev, [(labels, lab)], 6)
+    check_exact(dev, [(l2, x2)], 4)
+    # a single segment
+    check_exact(dev, [(np.zeros((5, 7), np.int64), x2[:5, :7])], 5)
+
+
+def components_of(values: np.ndarray):
+    """Number of 4-connected components of equal value (scipy sparse graph)."""
+    H, W = values.shape
+    idx = np.arange(H * W).reshape(H, W)
+    e1 = values[:, 1:] == values[:, :-1]
+    e2 = values[1:, :] == values[:-1, :]
+    rows = np.concatenate([idx[:, 1:][e1], idx[1:, :][e2]])
+    cols = np.concatenate([idx[:, :-1][e1], idx[:-1, :][e2]])
+    g = coo_matrix((np.ones(rows.size, np.int8), (rows, cols)), shape=(H * W, H * W))
+    return connected_components(g, directed=False)[0]
+
+
+def test_4k_gpu_labels_properties(dev):
+    say("two 3840x2160 images of the 4K law: EM to rel-tol 1e-5, labels, connectivity")
+    ims = synth.config5_batch(device=dev, n_images=2)
+    lab = synth.pack_batch(ims).to(dev)
+    m = GMMSP([(im.W, im.H) for im in ims], K=10000, device=dev)
+    m.init_seeds(lab)
+    m.em_iterate(lab, 200, 1e-5)
+    labels, _ = m.label(lab)
+    out, counts = m.connectivity(lab, labels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out2, counts2 = m.connectivity(lab, labels)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert torch.equal(out, out2) and np.array_equal(counts, counts2)     # deterministic
+    say("connectivity on 2 x 4K:", f"{dt * 1e3:.1f} ms;", "counts", counts.tolist())
+    g = m.grids[0]
+    lab_np = labels.cpu().numpy()
+    out_np = out.cpu().numpy()
+    for b in range(2):
+        L = lab_np[m.image_slice(b)].reshape(2160, 3840)
+        Oq = out_np[m.image_slice(b)].reshape(2160, 3840)
+        assert counts[b][0] == components_of(L)
+        vals, sizes = np.unique(Oq, return_counts=True)
+        assert counts[b][3] == vals.size == components_of(Oq)             # every segment connected
+        assert np.all(4 * sizes >= g.vx * g.vy)
+        assert np.all(Oq.ravel()[vals] == vals)                           # ids are own pixels
+        assert counts[b][2] == counts[b][0] - counts[b][3]
