@@ -978,10 +978,13 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
                    &C.list, &C.poff, &C.cpar, &C.mpar, &C.next, &C.tail};
   for (int i = 0; i < 13; ++i) *seg[i] = (int*)take(z.seg);
   C.colsum = (unsigned long long*)take(z.colsum);
-  int max_pix = 0;
-  for (const ImgDesc& I : h->img) max_pix = std::max(max_pix, I.W * I.H);
+  int max_pix = 0, max_tiles = 0;
+  for (const ImgDesc& I : h->img) {
+    max_pix = std::max(max_pix, I.W * I.H);
+    max_tiles = std::max(max_tiles, (int)conn_tiles(I.W, I.H));
+  }
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = conn_launch_components(C, h->P.img, h->n_img, max_pix, labels_dev, s);
+  hipError_t e = conn_launch_components(C, h->P.img, h->n_img, max_pix, max_tiles, labels_dev, s);
   int n_seg = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&n_seg, C.total, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -114,25 +114,83 @@ __device__ __forceinline__ int m_find(const int* mpar, int t) {
 }
 
 // ---- pixel components ------------------------------------------------------
+// A block labels a 32 x 32 tile in LDS (union-find with LDS atomics, local
+// raster order, which is the global order inside a tile), writes each pixel's
+// tile-local root as a global index, and the tile borders are then joined in
+// global memory.  Roots stay the minimum index of their set throughout.
 
-__global__ __launch_bounds__(kT) void k_cc_init(const ImgDesc* img, int* par) {
-  int b, j, W, H;
-  int64_t off;
-  if (!img_pixel(img, b, j, W, H, off)) return;
-  const int i = (int)(off + j);
-  par[i] = i;
+constexpr int kTile = 32;
+
+__device__ int lds_find(int* lp, int x) {
+  int y = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (y != x) {
+    x = y;
+    y = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  return x;
 }
 
-__global__ __launch_bounds__(kT) void k_cc_link(const ImgDesc* img, const int32_t* labels,
+__device__ void lds_unite(int* lp, int a, int b) {
+  a = lds_find(lp, a);
+  b = lds_find(lp, b);
+  while (a != b) {
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicCAS(lp + a, a, b);
+    if (old == a) return;
+    a = lds_find(lp, old);
+    b = lds_find(lp, b);
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_cc_tile(const ImgDesc* img, const int32_t* labels,
                                                 int* par) {
+  __shared__ int lp[kTile * kTile];
+  __shared__ int32_t ll[kTile * kTile];
+  const int b = blockIdx.y;
+  const ImgDesc& I = img[b];
+  const int W = I.W, H = I.H;
+  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  if ((int)blockIdx.x >= tiles_x * tiles_y) return;  // the whole block
+  const int x0 = (blockIdx.x % tiles_x) * kTile, y0 = (blockIdx.x / tiles_x) * kTile;
+  const int64_t off = I.pix_off;
+  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
+    const int x = x0 + l % kTile, y = y0 + l / kTile;
+    lp[l] = l;
+    ll[l] = (x < W && y < H) ? labels[off + (int64_t)y * W + x] : 0;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
+    const int tx = l % kTile, ty = l / kTile;
+    if (x0 + tx >= W || y0 + ty >= H) continue;
+    if (tx > 0 && ll[l - 1] == ll[l]) lds_unite(lp, l, l - 1);
+    if (ty > 0 && ll[l - kTile] == ll[l]) lds_unite(lp, l, l - kTile);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
+    const int x = x0 + l % kTile, y = y0 + l / kTile;
+    if (x >= W || y >= H) continue;
+    const int r = lds_find(lp, l);
+    par[off + (int64_t)y * W + x] = (int)(off + (int64_t)(y0 + r / kTile) * W + x0 + r % kTile);
+  }
+}
+
+// joins across tile borders: left edges and top edges of the tiles
+__global__ __launch_bounds__(kT) void k_cc_border(const ImgDesc* img, const int32_t* labels,
+                                                  int* par) {
   int b, j, W, H;
   int64_t off;
   if (!img_pixel(img, b, j, W, H, off)) return;
-  const int i = (int)(off + j);
   const int x = j % W, y = j / W;
+  const bool left = x > 0 && x % kTile == 0, top = y > 0 && y % kTile == 0;
+  if (!left && !top) return;
+  const int i = (int)(off + j);
   const int32_t l = labels[i];
-  if (x > 0 && labels[i - 1] == l) uf_unite(par, i, i - 1);
-  if (y > 0 && labels[i - W] == l) uf_unite(par, i, i - W);
+  if (left && labels[i - 1] == l) uf_unite(par, i, i - 1);
+  if (top && labels[i - W] == l) uf_unite(par, i, i - W);
 }
 
 __global__ __launch_bounds__(kT) void k_cc_flatten(const ImgDesc* img, int* par, int* flag) {
@@ -237,20 +295,51 @@ __global__ __launch_bounds__(kT) void k_seg_zero(int n_seg, int* size0,
   ccnt[s] = 0;
 }
 
-// size and integer colour sums: exact, so the atomics' order does not matter
+// size and integer colour sums: exact, so the atomics' order does not matter.
+// The 64 consecutive pixels of a wave are first summed per run of equal
+// segment (segmented scan with shuffles); the last lane of each run adds the
+// run's totals.
 __global__ __launch_bounds__(kT) void k_seg_stats(const ImgDesc* img, const float* lab,
                                                   const int* segid, int* size0,
                                                   unsigned long long* colsum) {
-  int b, j, W, H;
-  int64_t off;
-  if (!img_pixel(img, b, j, W, H, off)) return;
-  const int i = (int)(off + j);
-  const int s = segid[i];
-  atomicAdd(size0 + s, 1);
+  const int b = blockIdx.y;
+  const ImgDesc& I = img[b];
+  const int j = blockIdx.x * kT + threadIdx.x;
+  const int n = I.W * I.H;
+  if ((int)(blockIdx.x * kT) >= n) return;  // whole block beyond the image
+  const bool valid = j < n;
+  const int64_t i = I.pix_off + j;
+  const int lane = threadIdx.x & 63;
+  const int s = valid ? segid[i] : -1;
+  int cnt = valid ? 1 : 0;
+  long long q[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const long long q = (long long)rint((double)lab[3 * (int64_t)i + c] * 1048576.0);
-    atomicAdd(colsum + 3 * s + c, (unsigned long long)q);
+  for (int c = 0; c < 3; ++c)
+    q[c] = valid ? (long long)rint((double)lab[3 * i + c] * 1048576.0) : 0ll;
+  const int sl = __shfl_up(s, 1, 64);
+  int hp = (lane == 0 || sl != s) ? lane : 0;  // first lane of this lane's run
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(hp, o, 64);
+    if (lane >= o) hp = max(hp, t);
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int c0 = __shfl_up(cnt, o, 64);
+    const long long a0 = __shfl_up(q[0], o, 64), a1 = __shfl_up(q[1], o, 64),
+                    a2 = __shfl_up(q[2], o, 64);
+    if (lane - o >= hp) {
+      cnt += c0;
+      q[0] += a0;
+      q[1] += a1;
+      q[2] += a2;
+    }
+  }
+  const int sr = __shfl_down(s, 1, 64);
+  if (valid && (lane == 63 || sr != s)) {
+    atomicAdd(size0 + s, cnt);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) atomicAdd(colsum + 3 * s + c, (unsigned long long)q[c]);
   }
 }
 
@@ -436,14 +525,31 @@ __global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* seg
   out[i] = (int32_t)(seg_root[t] - off);
 }
 
+// per-image counts of small and merged segments: each block sums its
+// segments per image in LDS (a block's 256 consecutive segments span few
+// images) and adds each image's sums with one atomic per counter; the segment
+// count per image comes from the image's first segment index
 __global__ __launch_bounds__(kT) void k_counts(const ImgDesc* img, int n_seg, const int* seg_img,
                                                const int* size0, const int* mpar, int* counts) {
+  __shared__ int sb[kT], sc[kT][2];
   const int s = blockIdx.x * kT + threadIdx.x;
-  if (s >= n_seg) return;
-  int* c = counts + 4 * seg_img[s];
-  atomicAdd(c + 0, 1);
-  if (is_small(img, seg_img, size0, s)) atomicAdd(c + 1, 1);
-  if (mpar[s] != s) atomicAdd(c + 2, 1);
+  const bool valid = s < n_seg;
+  sb[threadIdx.x] = valid ? seg_img[s] : -1;
+  sc[threadIdx.x][0] = valid && is_small(img, seg_img, size0, s);
+  sc[threadIdx.x][1] = valid && mpar[s] != s;
+  __syncthreads();
+  const int b = sb[threadIdx.x];
+  // the first thread of each run of equal image sums the run and adds it
+  if (b < 0 || (threadIdx.x > 0 && sb[threadIdx.x - 1] == b)) return;
+  int c0 = 0, c1 = 0, c2 = 0;
+  for (int t = threadIdx.x; t < kT && sb[t] == b; ++t) {
+    ++c0;
+    c1 += sc[t][0];
+    c2 += sc[t][1];
+  }
+  atomicAdd(counts + 4 * b + 0, c0);
+  atomicAdd(counts + 4 * b + 1, c1);
+  atomicAdd(counts + 4 * b + 2, c2);
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
@@ -460,11 +566,16 @@ hipError_t scan(int* a, int n, int* bsum, int* total, hipStream_t s) {
 
 size_t conn_scan_blocks(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock); }
 
+size_t conn_tiles(int W, int H) {
+  return (size_t)((W + kTile - 1) / kTile) * (size_t)((H + kTile - 1) / kTile);
+}
+
 hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
-                                  int max_pixels, const int32_t* labels, hipStream_t s) {
+                                  int max_pixels, int max_tiles, const int32_t* labels,
+                                  hipStream_t s) {
   const dim3 g(blocks(max_pixels), n_img);
-  hipLaunchKernelGGL(k_cc_init, g, dim3(kT), 0, s, img, C.par);
-  hipLaunchKernelGGL(k_cc_link, g, dim3(kT), 0, s, img, labels, C.par);
+  hipLaunchKernelGGL(k_cc_tile, dim3(max_tiles, n_img), dim3(kT), 0, s, img, labels, C.par);
+  hipLaunchKernelGGL(k_cc_border, g, dim3(kT), 0, s, img, labels, C.par);
   hipLaunchKernelGGL(k_cc_flatten, g, dim3(kT), 0, s, img, C.par, C.scan);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -130,8 +130,10 @@ struct ConnPtrs {
   unsigned long long* colsum;  // [n_seg][3] quantised colour sums, then FP64 means
 };
 size_t conn_scan_blocks(int64_t n);
+size_t conn_tiles(int W, int H);  // 32 x 32 tiles of the component labelling
 hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
-                                  int max_pixels, const int32_t* labels, hipStream_t s);
+                                  int max_pixels, int max_tiles, const int32_t* labels,
+                                  hipStream_t s);
 hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
                              int n_seg, const float* lab, int32_t* out, hipStream_t s);
 
