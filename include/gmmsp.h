@@ -296,6 +296,35 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
                        int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t* counts_host,
                        void* stream);
 
+/* ------------------------------------------------------------------------
+ * Accuracy measures of Sec. IV for each image of the batch: boundary recall
+ * (BR), under-segmentation error (Eq. ue) and achievable segmentation
+ * accuracy (Eq. asa) of a superpixel label map against a ground-truth region
+ * map.
+ *
+ * A boundary pixel of a map is one whose right or lower neighbour carries
+ * another value.  BR = the fraction of ground-truth boundary pixels with a
+ * superpixel boundary pixel in the 5 x 5 square around them (1 when there
+ * is no ground-truth boundary).  UE = (1/N) sum_g sum_{k : |s_k n s_g| >
+ * 0.05 |s_k|} |s_k| - 1 (the comparison taken exactly as 20 |s_k n s_g| >
+ * |s_k|), ASA = (1/N) sum_k max_g |s_k n s_g|; N = W H.
+ *
+ * labels_dev: int32 per pixel of the batch with values in [0, K_b) (K_b = the
+ * image's n_x n_y, e.g. the output of gmmsp_label); gt_dev: int32 per pixel
+ * with values in [0, n_gt_host[b]).  Workspace (caller-allocated, 256-byte
+ * aligned): gmmsp_metrics_workspace_bytes, dominated by a K_b x n_gt[b] int32
+ * count table per image.  out_host: 3 doubles per image (BR, UE, ASA);
+ * sums_host (nullable): 4 int64 per image (recovered boundary pixels,
+ * ground-truth boundary pixels, the sum of Eq. ue, the sum of Eq. asa).
+ * Synchronises `stream`.  Errors: E_INVAL for null or misaligned pointers,
+ * n_gt < 1, or a value outside its range (found on the device; nothing is
+ * written out of bounds); E_SIZE for a short workspace or K_b n_gt >= 2^31.
+ * ------------------------------------------------------------------------ */
+int gmmsp_metrics_workspace_bytes(const gmmsp_handle* h, const int32_t* n_gt_host, size_t* bytes);
+int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_dev,
+                  const int32_t* n_gt_host, void* ws_dev, size_t ws_bytes, double* out_host,
+                  int64_t* sums_host, void* stream);
+
 const char* gmmsp_last_error(void);
 
 #ifdef __cplusplus

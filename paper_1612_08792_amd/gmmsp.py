@@ -307,6 +307,27 @@ class GMMSP:
                                        c_void_p(counts.ctypes.data), c_void_p(self._stream())))
         return out, counts
 
+    # -- accuracy measures (Sec. IV: BR, Eq. ue, Eq. asa) ----------------------
+    def metrics(self, labels: torch.Tensor, gt: torch.Tensor, n_gt):
+        """BR, UE, ASA per image of `labels` (int32, values in [0, K_b)) against
+        `gt` (int32, values in [0, n_gt[b])).  Returns (values (n_images, 3),
+        integer sums (n_images, 4))."""
+        for t, name in ((labels, "labels"), (gt, "gt")):
+            if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != self.n_pixels \
+                    or t.device != self.device:
+                raise ValueError(f"{name} must be a contiguous int32 tensor of n_pixels on the handle's device")
+        ngt = np.ascontiguousarray(np.broadcast_to(np.asarray(n_gt, dtype=np.int32), (self.n_images,)))
+        nbytes = c_size_t(0)
+        check(lib().gmmsp_metrics_workspace_bytes(self.handle, c_void_p(ngt.ctypes.data), byref(nbytes)))
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        out = np.zeros((self.n_images, 3), dtype=np.float64)
+        sums = np.zeros((self.n_images, 4), dtype=np.int64)
+        check(lib().gmmsp_metrics(self.handle, c_void_p(_ptr(labels)), c_void_p(_ptr(gt)),
+                                  c_void_p(ngt.ctypes.data), c_void_p(_ptr(ws)), nbytes.value,
+                                  c_void_p(out.ctypes.data), c_void_p(sums.ctypes.data),
+                                  c_void_p(self._stream())))
+        return out, sums
+
     # -- helpers -------------------------------------------------------------
     def image_slice(self, b: int) -> slice:
         return slice(int(self.pix_off[b]), int(self.pix_off[b + 1]))

@@ -1,0 +1,108 @@
+"""GPU accuracy measures (BR, Eq. ue, Eq. asa) through the C ABI against the
+CPU oracle: exact integer sums and values on the oracle EM's labels and on
+synthetic map pairs in an uneven batch; range errors; at 4K, an independent
+vectorised count."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+import synth
+from oracle import gmm_oracle as O
+from oracle import metrics_oracle as M
+from paper_1612_08792_amd.gmmsp import GMMSP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def gpu_metrics(dev, sizes, K, sp_maps, gt_maps, n_gt):
+    m = GMMSP(sizes, K=K, device=dev)
+    sp = torch.from_numpy(np.concatenate([s.astype(np.int32).ravel() for s in sp_maps])).to(dev)
+    gt = torch.from_numpy(np.concatenate([g.astype(np.int32).ravel() for g in gt_maps])).to(dev)
+    return m.metrics(sp, gt, n_gt), m
+
+
+def check(vals, sums, want, b):
+    assert list(sums[b]) == [want["br_hits"], want["br_total"], want["ue_sum"], want["asa_sum"]], b
+    assert vals[b, 0] == want["BR"] and vals[b, 1] == want["UE"] and vals[b, 2] == want["ASA"], b
+
+
+def test_oracle_em_labels_481x321(dev):
+    im = synth.config1_image()
+    g = O.make_grid(im.W, im.H, K=im.K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=10)
+    sp = ref["labels"].reshape(im.H, im.W)
+    gt = im.regions.numpy()
+    (vals, sums), _ = gpu_metrics(dev, [(im.W, im.H)], im.K, [sp], [gt], [40])
+    want = M.metrics(sp, gt)
+    check(vals, sums, want, 0)
+    say("481x321, T = 10: BR %.4f UE %.4f ASA %.4f" % tuple(vals[0]))
+
+
+def test_synthetic_pairs_uneven_batch(dev):
+    shapes = [(90, 61, 30, 9), (40, 33, 12, 5), (25, 25, 1, 3)]      # W, H, sp sites, gt sites
+    sp_maps, gt_maps, sizes, n_gt = [], [], [], []
+    for i, (W, H, ns, ng) in enumerate(shapes):
+        sp_maps.append(synth.voronoi_lab(W, H, ns, 3.0, 100 + i, 30).regions.numpy())
+        gt_maps.append(synth.voronoi_lab(W, H, ng, 3.0, 200 + i, 30).regions.numpy())
+        sizes.append((W, H))
+        n_gt.append(ng)
+    # grids of 10 x 6, 6 x 5 and 6 x 6 superpixels: at least as many as the sites
+    (vals, sums), m = gpu_metrics(dev, sizes, [60, 30, 30], sp_maps, gt_maps, n_gt)
+    for b in range(3):
+        assert m.grids[b].K >= shapes[b][2]
+        check(vals, sums, M.metrics(sp_maps[b], gt_maps[b]), b)
+
+
+def test_out_of_range_values_are_an_error(dev):
+    W, H = 30, 20
+    sp = np.zeros((H, W), np.int64)
+    gt = np.zeros((H, W), np.int64)
+    gt[3, 4] = 5                                     # n_gt = 2
+    with pytest.raises(Exception):
+        gpu_metrics(dev, [(W, H)], 6, [sp], [gt], [2])
+    sp[0, 0] = -1
+    gt[3, 4] = 1
+    with pytest.raises(Exception):
+        gpu_metrics(dev, [(W, H)], 6, [sp], [gt], [2])
+
+
+def test_4k_gpu_labels_against_vectorised_counts(dev):
+    say("two 3840x2160 images: EM to rel-tol 1e-5, labels, measures")
+    ims = synth.config5_batch(device=dev, n_images=2)
+    lab = synth.pack_batch(ims).to(dev)
+    m = GMMSP([(im.W, im.H) for im in ims], K=10000, device=dev)
+    m.init_seeds(lab)
+    m.em_iterate(lab, 200, 1e-5)
+    labels, _ = m.label(lab)
+    gt = torch.cat([im.regions.reshape(-1).to(dev) for im in ims]).to(torch.int32).contiguous()
+    vals, sums = m.metrics(labels, gt, 2000)
+    say("4K: BR/UE/ASA", vals.round(4).tolist())
+    L = labels.cpu().numpy()
+    G = gt.cpu().numpy()
+    for b in range(2):
+        sp = L[m.image_slice(b)].reshape(2160, 3840).astype(np.int64)
+        g = G[m.image_slice(b)].reshape(2160, 3840).astype(np.int64)
+        gb, sb = M.boundaries(g), M.boundaries(sp)
+        dist = ndimage.distance_transform_cdt(~sb, metric="chessboard")
+        keys, counts = np.unique(sp * 4096 + g, return_counts=True)
+        k = keys // 4096
+        size = np.bincount(k, weights=counts, minlength=m.grids[b].K).astype(np.int64)
+        best = np.zeros(m.grids[b].K, np.int64)
+        np.maximum.at(best, k, counts)
+        ue = int(size[k][20 * counts > size[k]].sum())
+        assert list(sums[b]) == [int((dist[gb] <= 2).sum()), int(gb.sum()), ue, int(best.sum())]
+        assert 0.0 <= vals[b, 1] and 0.0 < vals[b, 2] <= 1.0 and 0.0 <= vals[b, 0] <= 1.0
