@@ -284,7 +284,9 @@ int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t byte
  * gmmsp_connectivity: labels_dev (int32 per pixel of the batch, any values:
  *   only equality matters, e.g. the output of gmmsp_label) and lab_dev (the
  *   batch's Lab pixels) in; out_dev (int32 per pixel) receives the id of the
- *   segment the pixel ends in.  Needs the handle's geometry only (no
+ *   segment the pixel ends in (compact = 0), or its rank among the image's
+ *   final segments in id order, 0 .. final - 1 (compact != 0, e.g. as labels
+ *   for gmmsp_metrics).  Needs the handle's geometry only (no
  *   initialisation).  counts_host (nullable, 4 int32 per image): segments,
  *   small segments, merged segments, final segments.  Synchronises `stream`
  *   (the segment count is read back between two groups of launches).
@@ -293,8 +295,8 @@ int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t byte
  * ------------------------------------------------------------------------ */
 int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes);
 int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
-                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t* counts_host,
-                       void* stream);
+                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
+                       int32_t* counts_host, void* stream);
 
 /* ------------------------------------------------------------------------
  * Accuracy measures of Sec. IV for each image of the batch: boundary recall
@@ -309,21 +311,24 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
  * 0.05 |s_k|} |s_k| - 1 (the comparison taken exactly as 20 |s_k n s_g| >
  * |s_k|), ASA = (1/N) sum_k max_g |s_k n s_g|; N = W H.
  *
- * labels_dev: int32 per pixel of the batch with values in [0, K_b) (K_b = the
- * image's n_x n_y, e.g. the output of gmmsp_label); gt_dev: int32 per pixel
- * with values in [0, n_gt_host[b]).  Workspace (caller-allocated, 256-byte
- * aligned): gmmsp_metrics_workspace_bytes, dominated by a K_b x n_gt[b] int32
- * count table per image.  out_host: 3 doubles per image (BR, UE, ASA);
+ * labels_dev: int32 per pixel of the batch with values in [0, S_b), where
+ * S_b = n_sp_host[b], or the image's n_x n_y when n_sp_host is NULL (the
+ * output of gmmsp_label); gt_dev: int32 per pixel with values in
+ * [0, n_gt_host[b]).  Workspace (caller-allocated, 256-byte aligned):
+ * gmmsp_metrics_workspace_bytes, dominated by an S_b x n_gt[b] int32 count
+ * table per image.  out_host: 3 doubles per image (BR, UE, ASA);
  * sums_host (nullable): 4 int64 per image (recovered boundary pixels,
  * ground-truth boundary pixels, the sum of Eq. ue, the sum of Eq. asa).
  * Synchronises `stream`.  Errors: E_INVAL for null or misaligned pointers,
- * n_gt < 1, or a value outside its range (found on the device; nothing is
- * written out of bounds); E_SIZE for a short workspace or K_b n_gt >= 2^31.
+ * S_b or n_gt < 1, or a value outside its range (found on the device;
+ * nothing is written out of bounds); E_SIZE for a short workspace or
+ * S_b n_gt >= 2^31.
  * ------------------------------------------------------------------------ */
-int gmmsp_metrics_workspace_bytes(const gmmsp_handle* h, const int32_t* n_gt_host, size_t* bytes);
+int gmmsp_metrics_workspace_bytes(const gmmsp_handle* h, const int32_t* n_sp_host,
+                                  const int32_t* n_gt_host, size_t* bytes);
 int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_dev,
-                  const int32_t* n_gt_host, void* ws_dev, size_t ws_bytes, double* out_host,
-                  int64_t* sums_host, void* stream);
+                  const int32_t* n_sp_host, const int32_t* n_gt_host, void* ws_dev,
+                  size_t ws_bytes, double* out_host, int64_t* sums_host, void* stream);
 
 const char* gmmsp_last_error(void);
 

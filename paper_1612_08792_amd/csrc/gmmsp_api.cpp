@@ -955,8 +955,8 @@ int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
 }
 
 int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
-                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t* counts_host,
-                       void* stream) {
+                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
+                       int32_t* counts_host, void* stream) {
   if (!h || !lab_dev || !labels_dev || !out_dev || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
   if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
   if (h->n_pix >= ((int64_t)1 << 31) - 1)
@@ -990,7 +990,7 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity (components)");
   if (n_seg < 1 || n_seg > h->n_pix) return fail(GMMSP_E_STATE, "segment count %d out of range", n_seg);
-  e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, n_seg, lab_dev, out_dev, s);
+  e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, n_seg, lab_dev, compact ? 1 : 0, out_dev, s);
   if (e == hipSuccess && counts_host) {
     std::vector<int> c(4 * (size_t)h->n_img);
     e = hipMemcpyAsync(c.data(), C.counts, sizeof(int) * c.size(), hipMemcpyDeviceToHost, s);
@@ -1014,58 +1014,75 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
 namespace {
 
 struct MetricSizes {
-  size_t ngt, toff, tab, sb, brp, rows, sums, total;
-  int64_t tab_n;
+  size_t nlab, ngt, roff, toff, tab, sb, brp, rows, sums, total;
+  int64_t tab_n, n_rows;
   int max_pix;
+  std::vector<int32_t> lab;       // label count per image
+  std::vector<int64_t> row_off;   // n_img + 1
+  std::vector<int64_t> tab_off;
 };
 
-int metric_sizes(const gmmsp_handle* h, const int32_t* n_gt, MetricSizes* z) {
+int metric_sizes(const gmmsp_handle* h, const int32_t* n_sp, const int32_t* n_gt, MetricSizes* z) {
   z->tab_n = 0;
+  z->n_rows = 0;
   z->max_pix = 0;
+  z->lab.assign(h->n_img, 0);
+  z->row_off.assign(h->n_img + 1, 0);
+  z->tab_off.assign(h->n_img, 0);
   for (int32_t b = 0; b < h->n_img; ++b) {
+    const int64_t k = n_sp ? (int64_t)n_sp[b] : (int64_t)h->img[b].nx * h->img[b].ny;
+    if (k < 1) return fail(GMMSP_E_INVAL, "image %d: the label count must be >= 1", b);
     if (n_gt[b] < 1) return fail(GMMSP_E_INVAL, "image %d: n_gt must be >= 1", b);
-    const int64_t k = (int64_t)h->img[b].nx * h->img[b].ny;
-    if (k * n_gt[b] >= ((int64_t)1 << 31)) return fail(GMMSP_E_SIZE, "image %d: K x n_gt too large", b);
+    if (k * n_gt[b] >= ((int64_t)1 << 31)) return fail(GMMSP_E_SIZE, "image %d: labels x n_gt too large", b);
+    z->lab[b] = (int32_t)k;
+    z->tab_off[b] = z->tab_n;
     z->tab_n += k * n_gt[b];
+    z->row_off[b + 1] = z->row_off[b] + k;
     z->max_pix = std::max(z->max_pix, h->img[b].W * h->img[b].H);
   }
+  z->n_rows = z->row_off[h->n_img];
   const size_t n_img = (size_t)h->n_img;
+  z->nlab = align256(sizeof(int32_t) * n_img);
   z->ngt = align256(sizeof(int32_t) * n_img);
+  z->roff = align256(sizeof(int64_t) * (n_img + 1));
   z->toff = align256(sizeof(int64_t) * n_img);
   z->tab = align256(sizeof(int) * (size_t)z->tab_n);
   z->sb = align256((size_t)h->n_pix);
   z->brp = align256(sizeof(int) * 2 * n_img * (size_t)metrics_max_blocks(z->max_pix));
-  z->rows = align256(sizeof(int64_t) * (size_t)h->P.n_sp);
+  z->rows = align256(sizeof(int64_t) * (size_t)z->n_rows);
   z->sums = align256(sizeof(int64_t) * 4 * n_img + sizeof(int));
-  z->total = z->ngt + z->toff + z->tab + z->sb + z->brp + 2 * z->rows + z->sums;
+  z->total = z->nlab + z->ngt + z->roff + z->toff + z->tab + z->sb + z->brp + 2 * z->rows + z->sums;
   return GMMSP_OK;
 }
 
 }  // namespace
 
-int gmmsp_metrics_workspace_bytes(const gmmsp_handle* h, const int32_t* n_gt_host, size_t* bytes) {
+int gmmsp_metrics_workspace_bytes(const gmmsp_handle* h, const int32_t* n_sp_host,
+                                  const int32_t* n_gt_host, size_t* bytes) {
   if (!h || !n_gt_host || !bytes) return fail(GMMSP_E_INVAL, "null pointer");
   MetricSizes z;
-  const int rc = metric_sizes(h, n_gt_host, &z);
+  const int rc = metric_sizes(h, n_sp_host, n_gt_host, &z);
   if (rc) return rc;
   *bytes = z.total;
   return GMMSP_OK;
 }
 
 int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_dev,
-                  const int32_t* n_gt_host, void* ws_dev, size_t ws_bytes, double* out_host,
-                  int64_t* sums_host, void* stream) {
+                  const int32_t* n_sp_host, const int32_t* n_gt_host, void* ws_dev,
+                  size_t ws_bytes, double* out_host, int64_t* sums_host, void* stream) {
   if (!h || !labels_dev || !gt_dev || !n_gt_host || !ws_dev || !out_host)
     return fail(GMMSP_E_INVAL, "null pointer");
   if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
   MetricSizes z;
-  int rc = metric_sizes(h, n_gt_host, &z);
+  int rc = metric_sizes(h, n_sp_host, n_gt_host, &z);
   if (rc) return rc;
   if (ws_bytes < z.total) return fail(GMMSP_E_SIZE, "metrics workspace %zu < %zu bytes", ws_bytes, z.total);
   char* base = (char*)ws_dev;
   size_t t = 0;
   auto take = [&](size_t n) { void* p = base + t; t += n; return p; };
+  int32_t* d_nlab = (int32_t*)take(z.nlab);
   int32_t* d_ngt = (int32_t*)take(z.ngt);
+  int64_t* d_roff = (int64_t*)take(z.roff);
   int64_t* d_toff = (int64_t*)take(z.toff);
   int* d_tab = (int*)take(z.tab);
   uint8_t* d_sb = (uint8_t*)take(z.sb);
@@ -1074,27 +1091,25 @@ int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_
   int64_t* d_rasa = (int64_t*)take(z.rows);
   int64_t* d_sums = (int64_t*)take(z.sums);
   int* d_err = (int*)(d_sums + 4 * h->n_img);
-  std::vector<int64_t> toff(h->n_img);
-  int64_t o = 0;
-  for (int32_t b = 0; b < h->n_img; ++b) {
-    toff[b] = o;
-    o += (int64_t)h->img[b].nx * h->img[b].ny * n_gt_host[b];
-  }
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(d_ngt, n_gt_host, sizeof(int32_t) * h->n_img, hipMemcpyHostToDevice, s);
+  const size_t ni = (size_t)h->n_img;
+  hipError_t e = hipMemcpyAsync(d_nlab, z.lab.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_ngt, n_gt_host, sizeof(int32_t) * ni, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_toff, toff.data(), sizeof(int64_t) * h->n_img, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(d_roff, z.row_off.data(), sizeof(int64_t) * (ni + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = metrics_launch(h->P, z.max_pix, labels_dev, gt_dev, d_ngt, d_toff, z.tab_n, d_tab, d_sb,
-                       d_brp, d_rue, d_rasa, d_sums, d_err, s);
-  std::vector<int64_t> sums(4 * (size_t)h->n_img);
+    e = hipMemcpyAsync(d_toff, z.tab_off.data(), sizeof(int64_t) * ni, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = metrics_launch(h->P, z.max_pix, labels_dev, gt_dev, d_nlab, d_ngt, d_roff, z.n_rows, d_toff,
+                       z.tab_n, d_tab, d_sb, d_brp, d_rue, d_rasa, d_sums, d_err, s);
+  std::vector<int64_t> sums(4 * ni);
   int err = 0;
   if (e == hipSuccess)
     e = hipMemcpyAsync(sums.data(), d_sums, sizeof(int64_t) * sums.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_metrics");
-  if (err) return fail(GMMSP_E_INVAL, "a label or region id is outside [0, K) or [0, n_gt)");
+  if (err) return fail(GMMSP_E_INVAL, "a label or region id is outside [0, n_sp) or [0, n_gt)");
   for (int32_t b = 0; b < h->n_img; ++b) {
     const int64_t* q = sums.data() + 4 * b;
     const double n = (double)h->img[b].W * (double)h->img[b].H;

@@ -507,8 +507,18 @@ __global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, con
   (void)seg_root;
 }
 
+__global__ __launch_bounds__(kT) void k_root_flags(int n_seg, const int* mpar, int* flag) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s < n_seg) flag[s] = mpar[s] == s;
+}
+
+// output per pixel: the id of its final segment (compact = 0), or the rank of
+// that segment among the image's final segments in id order (compact = 1;
+// rank = final roots before it in the batch minus those before the image's
+// first segment)
 __global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* segid, int* mpar,
-                                              const int* seg_root, int32_t* out) {
+                                              const int* seg_root, const int* rank, int compact,
+                                              int32_t* out) {
   int b, j, W, H;
   int64_t off;
   if (!img_pixel(img, b, j, W, H, off)) return;
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* seg
     t = u;
     u = w;
   }
-  out[i] = (int32_t)(seg_root[t] - off);
+  out[i] = compact ? (int32_t)(rank[t] - rank[segid[off]]) : (int32_t)(seg_root[t] - off);
 }
 
 // per-image counts of small and merged segments: each block sums its
@@ -583,7 +593,8 @@ hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_i
 }
 
 hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
-                             int n_seg, const float* lab, int32_t* out, hipStream_t s) {
+                             int n_seg, const float* lab, int compact, int32_t* out,
+                             hipStream_t s) {
   const dim3 g(blocks(max_pixels), n_img);
   const unsigned gs = blocks(n_seg);
   hipLaunchKernelGGL(k_seg_assign, g, dim3(kT), 0, s, img, C.par, C.scan, C.segid, C.seg_root,
@@ -612,7 +623,12 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
   hipLaunchKernelGGL(k_merge, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.seg_root,
                      C.size0, C.cpar, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
                      reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail);
-  hipLaunchKernelGGL(k_final, g, dim3(kT), 0, s, img, C.segid, C.mpar, C.seg_root, out);
+  // the pixel-flag scan is free now: it ranks the final segments
+  hipLaunchKernelGGL(k_root_flags, dim3(gs), dim3(kT), 0, s, n_seg, C.mpar, C.scan);
+  e = scan(C.scan, n_seg, C.bsum, C.total, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, g, dim3(kT), 0, s, img, C.segid, C.mpar, C.seg_root, C.scan, compact,
+                     out);
   hipLaunchKernelGGL(k_zero, dim3(blocks(4 * n_img)), dim3(kT), 0, s, 4 * n_img, C.counts);
   hipLaunchKernelGGL(k_counts, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.mpar,
                      C.counts);

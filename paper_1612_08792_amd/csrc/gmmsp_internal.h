@@ -135,12 +135,14 @@ hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_i
                                   int max_pixels, int max_tiles, const int32_t* labels,
                                   hipStream_t s);
 hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
-                             int n_seg, const float* lab, int32_t* out, hipStream_t s);
+                             int n_seg, const float* lab, int compact, int32_t* out,
+                             hipStream_t s);
 
 // Accuracy measures (gmmsp_metrics.hip).
 int metrics_max_blocks(int max_pixels);
 hipError_t metrics_launch(const DevPtrs& P, int max_pixels, const int32_t* sp, const int32_t* gt,
-                          const int32_t* n_gt, const int64_t* tab_off, int64_t tab_n, int* tab,
+                          const int32_t* n_lab, const int32_t* n_gt, const int64_t* row_off,
+                          int64_t n_rows, const int64_t* tab_off, int64_t tab_n, int* tab,
                           uint8_t* sb, int* br_part, int64_t* row_ue, int64_t* row_asa,
                           int64_t* sums, int* err, hipStream_t s);
 

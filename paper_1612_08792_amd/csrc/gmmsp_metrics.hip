@@ -9,10 +9,11 @@
 //   * UE = (1/N) sum_g sum_{k : 20 |s_k n s_g| > |s_k|} |s_k| - 1 (eps = 0.05
 //     compared exactly), ASA = (1/N) sum_k max_g |s_k n s_g|.
 //
-// Superpixel labels lie in [0, K_b) (the image's seed grid) and region ids
-// in [0, G_b); the overlaps |s_k n s_g| are a dense K_b x G_b count table per
-// image, filled with integer atomics after a per-wave aggregation of runs of
-// equal (k, g) along the pixel row.  Every result is a ratio of exact integer
+// Superpixel labels lie in [0, S_b) (S_b given per image, by default the
+// image's seed-grid size K_b) and region ids in [0, G_b); the overlaps
+// |s_k n s_g| are a dense S_b x G_b count table per image (S_b G_b < 2^31),
+// filled with integer atomics after a per-wave aggregation of runs of equal
+// (k, g) along the pixel row.  Every result is a ratio of exact integer
 // counts.
 #include "gmmsp_internal.h"
 
@@ -47,8 +48,9 @@ __global__ __launch_bounds__(kT) void k_m_bnd(const ImgDesc* img, const int32_t*
 // overlap counts, and per block the boundary recall counts
 __global__ __launch_bounds__(kT) void k_m_pix(const ImgDesc* img, const int32_t* sp,
                                               const int32_t* gt, const uint8_t* sb,
-                                              const int32_t* n_gt, const int64_t* tab_off,
-                                              int* tab, int* br_part, int max_blocks, int* err) {
+                                              const int32_t* n_lab, const int32_t* n_gt,
+                                              const int64_t* tab_off, int* tab, int* br_part,
+                                              int max_blocks, int* err) {
   __shared__ int wsum[kT / 64][2];
   const int b = blockIdx.y;
   const ImgDesc& I = img[b];
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kT) void k_m_pix(const ImgDesc* img, const int32_t*
   const bool in = j < n;
   const int64_t i = I.pix_off + j;
   const int G = n_gt[b];
-  const int K = I.nx * I.ny;
+  const int K = n_lab[b];
   int key = -1;
   bool gb = false, hit = false;
   if (in) {
@@ -104,17 +106,23 @@ __global__ __launch_bounds__(kT) void k_m_pix(const ImgDesc* img, const int32_t*
 }
 
 // one wave per superpixel k (a row of its image's count table): |s_k|, the
-// leaking overlaps, the largest overlap
-__global__ __launch_bounds__(kT) void k_m_rows(const ImgDesc* img, const SpDesc* spd, int n_sp,
+// leaking overlaps, the largest overlap.  Rows are numbered image by image
+// (row_off[b] .. row_off[b + 1]).
+__global__ __launch_bounds__(kT) void k_m_rows(int n_img, const int64_t* row_off,
                                                const int32_t* n_gt, const int64_t* tab_off,
                                                const int* tab, int64_t* row_ue, int64_t* row_asa) {
-  const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  const int64_t row = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= n_sp) return;  // whole wave
-  const SpDesc d = spd[row];
-  const ImgDesc& I = img[d.img];
-  const int G = n_gt[d.img];
-  const int* r = tab + tab_off[d.img] + (int64_t)(d.ky * I.nx + d.kx) * G;
+  if (row >= row_off[n_img]) return;  // whole wave
+  int lo = 0, hi = n_img - 1;  // the image b with row_off[b] <= row < row_off[b + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (row_off[mid] <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  const int b = lo;
+  const int G = n_gt[b];
+  const int* r = tab + tab_off[b] + (row - row_off[b]) * G;
   int size = 0, best = 0;
   for (int g = lane; g < G; g += 64) {
     const int c = r[g];
@@ -138,21 +146,22 @@ __global__ __launch_bounds__(kT) void k_m_rows(const ImgDesc* img, const SpDesc*
 
 // one block per image: fixed-order sums of the block and row partials
 __global__ __launch_bounds__(kT) void k_m_reduce(const ImgDesc* img, const int* br_part,
-                                                 int max_blocks, const int64_t* row_ue,
-                                                 const int64_t* row_asa, int64_t* sums) {
+                                                 int max_blocks, const int64_t* row_off,
+                                                 const int64_t* row_ue, const int64_t* row_asa,
+                                                 int64_t* sums) {
   __shared__ int64_t red[4][kT];
   const int b = blockIdx.x;
   const ImgDesc& I = img[b];
   const int nb = (I.W * I.H + kT - 1) / kT;
-  const int K = I.nx * I.ny;
+  const int64_t r0 = row_off[b], r1 = row_off[b + 1];
   int64_t a[4] = {0, 0, 0, 0};
   for (int t = threadIdx.x; t < nb; t += kT) {
     a[0] += br_part[((int64_t)b * max_blocks + t) * 2 + 0];
     a[1] += br_part[((int64_t)b * max_blocks + t) * 2 + 1];
   }
-  for (int k = threadIdx.x; k < K; k += kT) {
-    a[2] += row_ue[I.sp_off + k];
-    a[3] += row_asa[I.sp_off + k];
+  for (int64_t k = r0 + threadIdx.x; k < r1; k += kT) {
+    a[2] += row_ue[k];
+    a[3] += row_asa[k];
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = a[c];
@@ -173,7 +182,8 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 int metrics_max_blocks(int max_pixels) { return (int)blocks(max_pixels); }
 
 hipError_t metrics_launch(const DevPtrs& P, int max_pixels, const int32_t* sp, const int32_t* gt,
-                          const int32_t* n_gt, const int64_t* tab_off, int64_t tab_n, int* tab,
+                          const int32_t* n_lab, const int32_t* n_gt, const int64_t* row_off,
+                          int64_t n_rows, const int64_t* tab_off, int64_t tab_n, int* tab,
                           uint8_t* sb, int* br_part, int64_t* row_ue, int64_t* row_asa,
                           int64_t* sums, int* err, hipStream_t s) {
   const unsigned fill_blocks = (unsigned)std::min<int64_t>(blocks(tab_n), 65536);
@@ -182,12 +192,12 @@ hipError_t metrics_launch(const DevPtrs& P, int max_pixels, const int32_t* sp, c
   const int mb = metrics_max_blocks(max_pixels);
   const dim3 g(mb, P.n_img);
   hipLaunchKernelGGL(k_m_bnd, g, dim3(kT), 0, s, P.img, sp, sb);
-  hipLaunchKernelGGL(k_m_pix, g, dim3(kT), 0, s, P.img, sp, gt, sb, n_gt, tab_off, tab, br_part,
-                     mb, err);
-  hipLaunchKernelGGL(k_m_rows, dim3((unsigned)((P.n_sp + 3) / 4)), dim3(kT), 0, s, P.img, P.sp,
-                     P.n_sp, n_gt, tab_off, tab, row_ue, row_asa);
-  hipLaunchKernelGGL(k_m_reduce, dim3(P.n_img), dim3(kT), 0, s, P.img, br_part, mb, row_ue,
-                     row_asa, sums);
+  hipLaunchKernelGGL(k_m_pix, g, dim3(kT), 0, s, P.img, sp, gt, sb, n_lab, n_gt, tab_off, tab,
+                     br_part, mb, err);
+  hipLaunchKernelGGL(k_m_rows, dim3((unsigned)((n_rows + 3) / 4)), dim3(kT), 0, s, P.n_img,
+                     row_off, n_gt, tab_off, tab, row_ue, row_asa);
+  hipLaunchKernelGGL(k_m_reduce, dim3(P.n_img), dim3(kT), 0, s, P.img, br_part, mb, row_off,
+                     row_ue, row_asa, sums);
   return hipGetLastError();
 }
 

@@ -286,11 +286,12 @@ class GMMSP:
 
     # -- connectivity post-processing (Algorithm 1, last step) ----------------
     def connectivity(self, lab: torch.Tensor, labels: torch.Tensor,
-                     out: torch.Tensor | None = None):
+                     out: torch.Tensor | None = None, compact: bool = False):
         """Merge the small disconnected segments of `labels` (int32 per pixel of
         the batch) into colour-nearest neighbours.  Returns (out, counts): out
         holds, per pixel, the image-local raster index of its final segment's
-        first pixel; counts (n_images, 4): segments, small, merged, final."""
+        first pixel (or, with compact, the segment's rank 0 .. final - 1 in its
+        image); counts (n_images, 4): segments, small, merged, final."""
         if labels.dtype != torch.int32 or not labels.is_contiguous() or \
                 labels.numel() != self.n_pixels or labels.device != self.device:
             raise ValueError("labels must be a contiguous int32 tensor of n_pixels on the handle's device")
@@ -304,25 +305,30 @@ class GMMSP:
         counts = np.zeros((self.n_images, 4), dtype=np.int32)
         check(lib().gmmsp_connectivity(self.handle, self._lab(lab), c_void_p(_ptr(labels)),
                                        c_void_p(_ptr(out)), c_void_p(_ptr(ws)), nbytes.value,
-                                       c_void_p(counts.ctypes.data), c_void_p(self._stream())))
+                                       1 if compact else 0, c_void_p(counts.ctypes.data),
+                                       c_void_p(self._stream())))
         return out, counts
 
     # -- accuracy measures (Sec. IV: BR, Eq. ue, Eq. asa) ----------------------
-    def metrics(self, labels: torch.Tensor, gt: torch.Tensor, n_gt):
-        """BR, UE, ASA per image of `labels` (int32, values in [0, K_b)) against
-        `gt` (int32, values in [0, n_gt[b])).  Returns (values (n_images, 3),
-        integer sums (n_images, 4))."""
+    def metrics(self, labels: torch.Tensor, gt: torch.Tensor, n_gt, n_sp=None):
+        """BR, UE, ASA per image of `labels` (int32, values in [0, n_sp[b]),
+        by default [0, K_b)) against `gt` (int32, values in [0, n_gt[b])).
+        Returns (values (n_images, 3), integer sums (n_images, 4))."""
         for t, name in ((labels, "labels"), (gt, "gt")):
             if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != self.n_pixels \
                     or t.device != self.device:
                 raise ValueError(f"{name} must be a contiguous int32 tensor of n_pixels on the handle's device")
         ngt = np.ascontiguousarray(np.broadcast_to(np.asarray(n_gt, dtype=np.int32), (self.n_images,)))
+        nsp = None if n_sp is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(n_sp, dtype=np.int32), (self.n_images,)))
+        nsp_p = c_void_p(nsp.ctypes.data) if nsp is not None else None
         nbytes = c_size_t(0)
-        check(lib().gmmsp_metrics_workspace_bytes(self.handle, c_void_p(ngt.ctypes.data), byref(nbytes)))
+        check(lib().gmmsp_metrics_workspace_bytes(self.handle, nsp_p, c_void_p(ngt.ctypes.data),
+                                                  byref(nbytes)))
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         out = np.zeros((self.n_images, 3), dtype=np.float64)
         sums = np.zeros((self.n_images, 4), dtype=np.int64)
-        check(lib().gmmsp_metrics(self.handle, c_void_p(_ptr(labels)), c_void_p(_ptr(gt)),
+        check(lib().gmmsp_metrics(self.handle, c_void_p(_ptr(labels)), c_void_p(_ptr(gt)), nsp_p,
                                   c_void_p(ngt.ctypes.data), c_void_p(_ptr(ws)), nbytes.value,
                                   c_void_p(out.ctypes.data), c_void_p(sums.ctypes.data),
                                   c_void_p(self._stream())))

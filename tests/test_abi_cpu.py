@@ -119,11 +119,11 @@ def test_connectivity_rejects_bad_arguments_before_any_device_work():
     L = _lib.lib()
     p = c_void_p(0x1000)
     assert L.gmmsp_conn_workspace_bytes(None, byref(c_size_t(0))) == _lib.GMMSP_E_INVAL
-    assert L.gmmsp_connectivity(None, p, p, p, p, 1 << 20, None, None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_connectivity(None, p, p, p, p, 1 << 20, 0, None, None) == _lib.GMMSP_E_INVAL
 
 
 def test_metrics_rejects_bad_arguments_before_any_device_work():
     L = _lib.lib()
     p = c_void_p(0x1000)
-    assert L.gmmsp_metrics_workspace_bytes(None, p, byref(c_size_t(0))) == _lib.GMMSP_E_INVAL
-    assert L.gmmsp_metrics(None, p, p, p, p, 1 << 20, p, None, None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_metrics_workspace_bytes(None, None, p, byref(c_size_t(0))) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_metrics(None, p, p, None, p, p, 1 << 20, p, None, None) == _lib.GMMSP_E_INVAL

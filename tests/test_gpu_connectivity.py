@@ -43,11 +43,18 @@ def run_gpu(dev, items, v):
 
 
 def check_exact(dev, items, v):
-    got, counts, _ = run_gpu(dev, items, v)
+    got, counts, m = run_gpu(dev, items, v)
+    labels = torch.from_numpy(np.concatenate([l.astype(np.int32).ravel() for l, _ in items])).to(dev)
+    lab = torch.from_numpy(np.concatenate([x.astype(np.float32).reshape(-1) for _, x in items])).to(dev)
+    comp, _ = m.connectivity(lab, labels, compact=True)
+    comp = comp.cpu().numpy()
     for b, (labels, lab) in enumerate(items):
         want, info = C.enforce_connectivity(labels, lab, v, v)
         assert np.array_equal(got[b], want), b
         assert list(counts[b]) == [info["segments"], info["small"], info["merged"], info["final"]], b
+        # compact form: the rank of each final segment id in the image
+        ranks = np.searchsorted(np.unique(want), want)
+        assert np.array_equal(comp[m.image_slice(b)].reshape(want.shape), ranks), b
     return counts
 
 

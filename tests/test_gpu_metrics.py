@@ -10,6 +10,7 @@ import torch
 from scipy import ndimage
 
 import synth
+from oracle import conn_oracle as C
 from oracle import gmm_oracle as O
 from oracle import metrics_oracle as M
 from paper_1612_08792_amd.gmmsp import GMMSP
@@ -50,6 +51,26 @@ def test_oracle_em_labels_481x321(dev):
     want = M.metrics(sp, gt)
     check(vals, sums, want, 0)
     say("481x321, T = 10: BR %.4f UE %.4f ASA %.4f" % tuple(vals[0]))
+
+
+def test_after_connectivity_481x321(dev):
+    # Algorithm 1 complete: labels, connectivity, then the measures, on the
+    # compact segment ranks (label count per image = final segments)
+    im = synth.config1_image()
+    g = O.make_grid(im.W, im.H, K=im.K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=10)
+    labels = ref["labels"].reshape(im.H, im.W)
+    out, info = C.enforce_connectivity(labels, im.lab.numpy(), g.vx, g.vy)
+    ranks = np.searchsorted(np.unique(out), out)
+    want = M.metrics(ranks, im.regions.numpy())
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    lab = im.lab.reshape(-1).to(dev)
+    sp = torch.from_numpy(labels.astype(np.int32).ravel()).to(dev)
+    comp, counts = m.connectivity(lab, sp, compact=True)
+    gt = im.regions.reshape(-1).to(dev).to(torch.int32).contiguous()
+    vals, sums = m.metrics(comp, gt, 40, n_sp=int(counts[0][3]))
+    check(vals, sums, want, 0)
+    say("481x321, T = 10, connected: BR %.4f UE %.4f ASA %.4f" % tuple(vals[0]))
 
 
 def test_synthetic_pairs_uneven_batch(dev):
