@@ -354,7 +354,31 @@ def run_em(lab, g: Grid, p: Params | None = None, max_iters: int = 10,
 
 # ---------------------------------------------------------------------------
 # Parameter export layout: mu_x mu_y mu_L mu_a mu_b S_xx S_xy S_yy S_LL S_aa S_ab S_bb N_k
+# (cov_mode 0); with the 3x3 colour block (cov_mode 1):
+# mu_x mu_y mu_L mu_a mu_b S_xx S_xy S_yy S_LL S_La S_Lb S_aa S_ab S_bb N_k
 # ---------------------------------------------------------------------------
+
+ROW3 = [(0, 0), (0, 1), (1, 1), (2, 2), (2, 3), (2, 4), (3, 3), (3, 4), (4, 4)]
+
+
+def theta_to_rows3(theta: Theta) -> np.ndarray:
+    K = theta.mu.shape[0]
+    out = np.zeros((K, 15))
+    out[:, 0:5] = theta.mu
+    for c, (i, j) in enumerate(ROW3):
+        out[:, 5 + c] = theta.sigma[:, i, j]
+    out[:, 14] = 0.0 if theta.mass is None else theta.mass
+    return out
+
+
+def rows3_to_theta(rows: np.ndarray) -> Theta:
+    rows = np.asarray(rows, dtype=np.float64)
+    K = rows.shape[0]
+    s = np.zeros((K, D, D))
+    for c, (i, j) in enumerate(ROW3):
+        s[:, i, j] = s[:, j, i] = rows[:, 5 + c]
+    return Theta(rows[:, 0:5].copy(), s, rows[:, 14].copy())
+
 
 def theta_to_rows(theta: Theta) -> np.ndarray:
     K = theta.mu.shape[0]

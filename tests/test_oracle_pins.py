@@ -389,3 +389,17 @@ def test_init_seed_pixels_hand_values():
     for k, (x, y) in [(0, (9, 9)), (26, (28, 28)), (399, (465, 294))]:
         np.testing.assert_array_equal(th.mu[k], z[y, x])
     np.testing.assert_array_equal(th.sigma[5], np.diag([361.0, 361.0, 64.0, 64.0, 64.0]))
+
+
+def test_row_layout_of_the_3x3_colour_block():
+    im = synth.voronoi_lab(60, 45, 6, 3.0, 9, 12)
+    g = O.make_grid(60, 45, K=12)
+    res = O.run_em(im.lab.numpy(), g, O.Params(cov_mode=1), max_iters=3)
+    th = res["theta"]
+    rows = O.theta_to_rows3(th)
+    back = O.rows3_to_theta(rows)
+    np.testing.assert_array_equal(back.mu, th.mu)
+    np.testing.assert_array_equal(back.sigma, th.sigma)
+    # the colour block is a full 3x3 after the M-step (L-a, L-b correlations kept)
+    assert np.any(rows[:, 9] != 0) and np.any(rows[:, 10] != 0)
+    assert np.all(th.sigma[:, :2, 2:] == 0)
