@@ -53,7 +53,9 @@ typedef struct gmmsp_params {
   double eps_s;         /* spatial eigenvalue floor (paper: 2, Sec. III-C)           */
   double eps_c;         /* colour eigenvalue floor (paper: 8, Sec. IV-A)             */
   double lambda;        /* initial colour standard deviation (paper: 8, Sec. IV-A)   */
-  int32_t cov_mode;     /* 0: blocks {(x,y), L, (a,b)} (Eq. BlockSigma1); only 0     */
+  int32_t cov_mode;     /* 0: blocks {(x,y), L, (a,b)} (Eq. BlockSigma1);            */
+                        /* 1: blocks {(x,y), (L,a,b)} (Eq. BlockSigma); one value    */
+                        /*    for every image of a batch                             */
   double n_min;         /* a superpixel with mass sum_i R_ik < n_min keeps theta_k   */
 } gmmsp_params;
 
@@ -65,11 +67,14 @@ typedef struct gmmsp_grid_info {
 
 typedef struct gmmsp_handle gmmsp_handle;
 
-/* Parameter row exported per superpixel, 13 doubles:
+/* Parameter row exported per superpixel, 13 doubles with cov_mode 0:
  *   mu_x mu_y mu_L mu_a mu_b  S_xx S_xy S_yy  S_LL  S_aa S_ab S_bb  N_k
  * (mean, the blocks of Sigma_k per Eq. BlockSigma1, and the mass
- * N_k = sum_{i in I_k} R_ik of the M-step that produced them). */
+ * N_k = sum_{i in I_k} R_ik of the M-step that produced them); 15 doubles with
+ * cov_mode 1 (the 3x3 colour block of Eq. BlockSigma):
+ *   mu_x mu_y mu_L mu_a mu_b  S_xx S_xy S_yy  S_LL S_La S_Lb S_aa S_ab S_bb  N_k */
 #define GMMSP_THETA_ROW 13
+#define GMMSP_THETA_ROW3 15
 
 /* Largest number of E-steps whose log-likelihood one handle records per image
  * between two initialisations. */
@@ -82,7 +87,8 @@ int gmmsp_grid(const gmmsp_params* params, gmmsp_grid_info* out);
 
 /* Host only.  Device workspace, in bytes, for a batch of n_images images with
  * parameters params[0..n_images-1].  Errors: those of gmmsp_grid, E_INVAL for
- * cov_mode != 0 or a non-positive eps_s, eps_c, lambda. */
+ * cov_mode not 0 or 1, different cov_mode values in one batch, or a
+ * non-positive eps_s, eps_c, lambda. */
 int gmmsp_workspace_bytes(int32_t n_images, const gmmsp_params* params, size_t* bytes);
 
 /* Create a handle over caller-owned device workspace (at least
@@ -106,7 +112,8 @@ int gmmsp_image_grid(const gmmsp_handle* h, int32_t b, gmmsp_grid_info* out);
  * image.  lab_dev: packed batch (see above). */
 int gmmsp_init_seeds(gmmsp_handle* h, const float* lab_dev, void* stream);
 
-/* Set theta for every superpixel from rows of GMMSP_THETA_ROW doubles (device
+/* Set theta for every superpixel from rows of GMMSP_THETA_ROW (cov_mode 1:
+ * GMMSP_THETA_ROW3) doubles (device
  * memory, batch order; N_k ignored), applying the shape-control eigenvalue floors
  * of Eqs. mlams and mlamc, and reset the iteration state.  This is the warm-start
  * entry point and the resume hook. */
@@ -115,7 +122,8 @@ int gmmsp_set_params_dev(gmmsp_handle* h, const double* theta_dev, void* stream)
 /* The same from host memory (copied on `stream`, which is synchronised). */
 int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream);
 
-/* Copy theta (rows of GMMSP_THETA_ROW doubles, batch order) to the host. */
+/* Copy theta (rows of GMMSP_THETA_ROW, cov_mode 1: GMMSP_THETA_ROW3, doubles,
+ * batch order) to the host. */
 int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream);
 
 /* EM iterations (Algorithm 1, steps 2-6).  Each pass t evaluates the E-step
@@ -155,7 +163,8 @@ int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream);
 /* Schedule of the statistics pass: how many 64-lane waves share one v_x x v_y
  * cell (1, 2 or 4; default 1).  More waves per cell raise the parallelism of
  * small batches; every schedule gives the same result up to the grouping of the
- * FP64 sums (each schedule is itself bitwise repeatable). */
+ * FP64 sums (each schedule is itself bitwise repeatable).  With cov_mode 1 only
+ * 1 is accepted (E_INVAL otherwise). */
 #define GMMSP_MAX_WAVES_PER_CELL 4
 int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell);
 int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
@@ -163,7 +172,8 @@ int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
 /* Autotuner: times `passes` statistics passes (after one untimed pass) from the
  * grid initialisation for each schedule 1, 2, 4 with HIP events on `stream`,
  * keeps the fastest (ties to fewer waves), and leaves the handle initialised
- * by gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times. */
+ * by gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times (-1
+ * for a schedule not timed; with cov_mode 1 only schedule 1 is). */
 int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
                    int32_t* chosen, void* stream);
 
@@ -224,7 +234,8 @@ typedef enum gmmsp_ws_buffer {
 } gmmsp_ws_buffer;
 
 /* Device workspace of the warm start for this handle's batch, and attaching it
- * (builds the seed-grid neighbour table on `stream`, then synchronises it). */
+ * (builds the seed-grid neighbour table on `stream`, then synchronises it).
+ * The network predicts the split colour blocks: E_INVAL with cov_mode 1. */
 int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes);
 int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream);
 

@@ -17,6 +17,7 @@ GMMSP_E_SIZE = -2
 GMMSP_E_HIP = -3
 GMMSP_E_STATE = -5
 THETA_ROW = 13
+THETA_ROW3 = 15
 LL_CAP = 4096
 
 

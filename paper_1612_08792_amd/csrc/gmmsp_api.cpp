@@ -67,7 +67,8 @@ int grid_of(const gmmsp_params* p, gmmsp_grid_info* g) {
 int check_params(const gmmsp_params* p) {
   if (!(p->eps_s > 0) || !(p->eps_c > 0) || !(p->lambda > 0) || !(p->n_min >= 0))
     return fail(GMMSP_E_INVAL, "eps_s, eps_c, lambda must be > 0 and n_min >= 0");
-  if (p->cov_mode != 0) return fail(GMMSP_E_INVAL, "cov_mode %d is not supported", p->cov_mode);
+  if (p->cov_mode != 0 && p->cov_mode != 1)
+    return fail(GMMSP_E_INVAL, "cov_mode %d is not supported (0 or 1)", p->cov_mode);
   return GMMSP_OK;
 }
 
@@ -77,6 +78,7 @@ struct Layout {
   size_t img, state, ll_hist, cell, sp, theta, rec, part, llp, n_done, total;
   int32_t n_cell = 0, n_sp = 0;
   int64_t n_pix = 0;
+  int32_t cov3 = 0;
 };
 
 int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>* descs) {
@@ -89,6 +91,8 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
     if (rc) return fail(rc, "image %d: %s", b, g_err.c_str());
     rc = check_params(&params[b]);
     if (rc) return fail(rc, "image %d: %s", b, g_err.c_str());
+    if (params[b].cov_mode != params[0].cov_mode)
+      return fail(GMMSP_E_INVAL, "image %d: every image of a batch needs the same cov_mode", b);
     if (descs) {
       ImgDesc& d = (*descs)[b];
       memset(&d, 0, sizeof(d));
@@ -116,8 +120,9 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
   L->ll_hist = o; o = align256(o + sizeof(double) * (size_t)kLLCap * n);
   L->cell = o;    o = align256(o + sizeof(CellDesc) * n_cell);
   L->sp = o;      o = align256(o + sizeof(SpDesc) * n_sp);
-  L->theta = o;   o = align256(o + sizeof(double) * kThetaRow * n_sp);
-  L->rec = o;     o = align256(o + sizeof(float) * kRecFloats * kSlots * n_cell);
+  L->cov3 = params[0].cov_mode == 1;
+  L->theta = o;   o = align256(o + sizeof(double) * (L->cov3 ? kThetaRow3 : kThetaRow) * n_sp);
+  L->rec = o;     o = align256(o + sizeof(float) * (L->cov3 ? kRec3 : kRecFloats) * kSlots * n_cell);
   L->part = o;    o = align256(o + sizeof(double) * kPartStride * kMaxWpc * n_cell);
   L->llp = o;     o = align256(o + sizeof(double) * kMaxWpc * n_cell);
   L->n_done = o;  o = align256(o + sizeof(int32_t));
@@ -287,6 +292,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.n_cell = L.n_cell;
   P.n_sp = L.n_sp;
   P.wpc = 1;
+  P.cov3 = L.cov3;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -357,7 +363,7 @@ int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
   if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
   // stage the rows in the partials area, which the next pass overwrites anyway
-  const size_t bytes = sizeof(double) * kThetaRow * (size_t)h->P.n_sp;
+  const size_t bytes = sizeof(double) * (h->P.cov3 ? kThetaRow3 : kThetaRow) * (size_t)h->P.n_sp;
   if (bytes > sizeof(double) * kPartStride * (size_t)h->P.n_cell)
     return fail(GMMSP_E_SIZE, "staging area too small");
   hipError_t e = hipMemcpyAsync(h->P.part, theta_host, bytes, hipMemcpyHostToDevice, s);
@@ -372,7 +378,8 @@ int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
 int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
   if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(theta_host, h->P.theta, sizeof(double) * kThetaRow * (size_t)h->P.n_sp,
+  const size_t row = h->P.cov3 ? kThetaRow3 : kThetaRow;
+  hipError_t e = hipMemcpyAsync(theta_host, h->P.theta, sizeof(double) * row * (size_t)h->P.n_sp,
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_get_params");
@@ -590,6 +597,8 @@ int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (waves_per_cell != 1 && waves_per_cell != 2 && waves_per_cell != 4)
     return fail(GMMSP_E_INVAL, "waves per cell must be 1, 2 or 4");
+  if (h->P.cov3 && waves_per_cell != 1)
+    return fail(GMMSP_E_INVAL, "the 3x3 colour block (cov_mode 1) runs one wave per cell");
   h->P.wpc = waves_per_cell;
   return GMMSP_OK;
 }
@@ -613,12 +622,15 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
   const int32_t cand[3] = {1, 2, 4};
+  const int n_cand = h->P.cov3 ? 1 : 3;  // the 3x3 colour block has one schedule
+  if (ms_host)
+    for (int c = 0; c < 3; ++c) ms_host[c] = -1.0;
   double best = 0.0;
   int32_t pick = 1;
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+  for (int c = 0; c < n_cand && e == hipSuccess; ++c) {
     h->P.wpc = cand[c];
     e = launch_reset_state(h->P, s);
     if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
@@ -764,12 +776,14 @@ hipError_t ws_forward_range(gmmsp_handle* h, const float* params, int p0, int p1
 
 int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(GMMSP_E_INVAL, "null pointer");
+  if (h->P.cov3) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
   *bytes = ws_sizes(h).total;
   return GMMSP_OK;
 }
 
 int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream) {
   if (!h || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (h->P.cov3) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
   if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
   const WsLayoutSizes z = ws_sizes(h);
   if (bytes < z.total) return fail(GMMSP_E_SIZE, "warm-start workspace %zu < %zu bytes", bytes, z.total);

@@ -16,6 +16,11 @@ constexpr int kThetaRow = 13;      // doubles per superpixel in the FP64 master
 constexpr int kLLCap = 4096;       // log-likelihood history entries per image
 constexpr int kWavesPerBlock = 4;  // 64-lane waves per block of the per-cell kernels
 constexpr int kMaxWpc = 4;         // largest number of waves sharing one cell
+// the unified 3x3 colour block (cov_mode 1)
+constexpr int kRec3 = 20;          // floats per cell-slot record
+constexpr int kStats3 = 15;        // N, S1 (5), S2 (xx xy yy LL La Lb aa ab bb)
+constexpr int kPart3 = 136;        // doubles per cell: 9 x 15 statistics, 1 pad
+constexpr int kThetaRow3 = 15;     // doubles per superpixel in the FP64 master
 
 // Cell-slot record: the parameters of the superpixel in slot s of cell c, in
 // float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
@@ -77,6 +82,7 @@ struct DevPtrs {
   int32_t* n_done;          // images that have stopped
   int32_t n_img, n_cell, n_sp;
   int32_t wpc;              // waves per cell of the statistics pass (1, 2 or 4)
+  int32_t cov3;             // 1: the 3x3 colour block (cov_mode 1), kernels of gmmsp_cov3.hip
 };
 
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
@@ -90,6 +96,16 @@ hipError_t launch_finalize(const DevPtrs& P, hipStream_t s);
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s);
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s);
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
+
+// The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
+// 2 responsibilities, 3 candidates.  The launchers above dispatch to these
+// when P.cov3 is set.
+hipError_t launch3_clear_records(const DevPtrs& P, hipStream_t s);
+hipError_t launch3_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s);
+hipError_t launch3_set_params(const DevPtrs& P, const double* rows, hipStream_t s);
+hipError_t launch3_cells(const DevPtrs& P, int mode, const float* lab, int32_t* out_i,
+                         float* out_f, hipStream_t s);
+hipError_t launch3_finalize(const DevPtrs& P, hipStream_t s);
 
 // Warm-start network launchers (gmmsp_warmstart.hip).
 hipError_t ws_launch_nbr(const DevPtrs& P, int32_t* nbr, hipStream_t s);

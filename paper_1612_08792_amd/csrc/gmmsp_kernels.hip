@@ -13,22 +13,11 @@
 // nine cells of its window I_k in a fixed order: no atomics, bitwise
 // repeatable.
 #include "gmmsp_internal.h"
+#include "gmmsp_wave.h"
 
 #include <math.h>
 
 namespace gmmsp {
-
-#define AS4 __attribute__((address_space(4)))
-
-// Uniform reads through the constant address space compile to scalar loads.
-template <typename T>
-__device__ __forceinline__ const AS4 T* cptr(const T* p) {
-  return (const AS4 T*)(p);
-}
-
-constexpr double kLog2e = 1.4426950408889634074;
-constexpr double kLn2 = 0.69314718055994530942;
-constexpr double kLn2Pi = 1.8378770664093454836;
 
 // ---------------------------------------------------------------------------
 // FP64 shape control of one symmetric 2x2 block [[a, b], [b, c]]
@@ -262,98 +251,6 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
   l = fmaf(-u1, u1, l);
   l = fmaf(-u2, u2, l);
   return l;
-}
-
-// Butterfly reduce-scatter of per-lane sums across a 64-lane wave.  Each step
-// halves the number of values: in a pair of partner lanes the one whose keep
-// bit is 0 keeps the even entries summed with its partner's, the other the odd
-// ones.  Keep bits go 5, 4, 3, 2, 1, 0, so after the six steps lane l holds the
-// wave totals of entries bitrev6(l) and 64 + bitrev6(l).
-#ifndef GMMSP_REDUCE_DPP
-#define GMMSP_REDUCE_DPP 1
-#endif
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// partner = lane ^ MASK through ds_bpermute
-template <int N, int MASK, int CAP>
-__device__ __forceinline__ void bfly_shfl(float (&v)[CAP], int lane) {
-  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-  const bool hi = (lane & MASK) != 0;
-  if (N & 1) v[N] = 0.f;  // odd count: the pair partner of the last entry is zero
-#pragma unroll
-  for (int i = 0; i < (N + 1) / 2; ++i) {
-    const float a = v[2 * i], b = v[2 * i + 1];
-    const float send = hi ? a : b;
-    const float keep = hi ? b : a;
-    v[i] = keep + __shfl_xor(send, MASK, 64);
-  }
-}
-
-// keep bit 5 (lanes 0-31 keep even entries): v_permlane32_swap exchanges the
-// upper half of the first operand with the lower half of the second.
-template <int N, int CAP>
-__device__ __forceinline__ void bfly_swap32(float (&v)[CAP]) {
-  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-  if (N & 1) v[N] = 0.f;
-#pragma unroll
-  for (int i = 0; i < (N + 1) / 2; ++i) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]),
-                                                    __float_as_uint(v[2 * i + 1]), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-}
-
-// keep bit 4: v_permlane16_swap exchanges odd 16-lane rows of the first operand
-// with even rows of the second.
-template <int N, int CAP>
-__device__ __forceinline__ void bfly_swap16(float (&v)[CAP]) {
-  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-  if (N & 1) v[N] = 0.f;
-#pragma unroll
-  for (int i = 0; i < (N + 1) / 2; ++i) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[2 * i]),
-                                                    __float_as_uint(v[2 * i + 1]), false, false);
-    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-}
-
-// keep bit BIT, partner given by the DPP control CTRL (an involution inside a
-// 16-lane row that flips BIT and keeps the higher bits)
-template <int N, int BIT, int CTRL, int CAP>
-__device__ __forceinline__ void bfly_dpp(float (&v)[CAP], int lane) {
-  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-  const bool hi = ((lane >> BIT) & 1) != 0;
-  if (N & 1) v[N] = 0.f;
-#pragma unroll
-  for (int i = 0; i < (N + 1) / 2; ++i) {
-    const float a = v[2 * i], b = v[2 * i + 1];
-    const float send = hi ? a : b;
-    const float keep = hi ? b : a;
-    v[i] = keep + dpp<CTRL>(send);
-  }
-}
-
-template <int CAP>
-__device__ __forceinline__ void wave_reduce_scatter_117(float (&v)[CAP], int lane) {
-#if GMMSP_REDUCE_DPP
-  bfly_swap32<117>(v);
-  bfly_swap16<59>(v);
-  bfly_dpp<30, 3, 0x128>(v, lane);  // row_ror:8, partner lane ^ 8
-  bfly_dpp<15, 2, 0x141>(v, lane);  // row_half_mirror, partner lane ^ 7
-  bfly_dpp<8, 1, 0x4E>(v, lane);    // quad_perm [2,3,0,1], partner lane ^ 2
-  bfly_dpp<4, 0, 0xB1>(v, lane);    // quad_perm [1,0,3,2], partner lane ^ 1
-#else
-  bfly_shfl<117, 32>(v, lane);
-  bfly_shfl<59, 16>(v, lane);
-  bfly_shfl<30, 8>(v, lane);
-  bfly_shfl<15, 4>(v, lane);
-  bfly_shfl<8, 2>(v, lane);
-  bfly_shfl<4, 1>(v, lane);
-#endif
 }
 
 // record offsets held in vector registers for the whole cell (see VOff)
@@ -637,7 +534,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       accumulate_stats<1>(rec, acc, e, inv, xr, yr, L, A, B);
     }
-    wave_reduce_scatter_117(acc, lane);
+    wave_reduce_scatter<kSlots * kStats>(acc, lane);
     const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
     double* part = P.part + ((size_t)sub * P.n_cell + cell) * kPartStride;
     part[r] = (double)acc[0];
@@ -818,6 +715,7 @@ static inline unsigned blocks_for(size_t n, unsigned per) {
 }
 
 hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s) {
+  if (P.cov3) return launch3_clear_records(P, s);
   const size_t n = (size_t)P.n_cell * kSlots;
   hipLaunchKernelGGL(k_clear_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, P.rec, n);
   return hipGetLastError();
@@ -829,16 +727,19 @@ hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s) {
 }
 
 hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s) {
+  if (P.cov3) return launch3_init_seeds(P, lab, s);
   hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab);
   return hipGetLastError();
 }
 
 hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s) {
+  if (P.cov3) return launch3_set_params(P, rows, s);
   hipLaunchKernelGGL(k_set_params, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, rows);
   return hipGetLastError();
 }
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
+  if (P.cov3) return launch3_cells(P, 0, lab, nullptr, nullptr, s);
   const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
   if (P.wpc == 4)
     hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
@@ -858,24 +759,32 @@ hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
+  if (P.cov3) return launch3_finalize(P, s);
   hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s) {
-  hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
-                     s, P, lab, labels, (float*)nullptr);
+  if (P.cov3) {
+    const hipError_t e = launch3_cells(P, 1, lab, labels, nullptr, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
+                       s, P, lab, labels, (float*)nullptr);
+  }
   hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, 1, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s) {
+  if (P.cov3) return launch3_cells(P, 2, lab, nullptr, R, s);
   hipLaunchKernelGGL(k_cells<M_EXPORT_R>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256),
                      0, s, P, lab, (int32_t*)nullptr, R);
   return hipGetLastError();
 }
 
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s) {
+  if (P.cov3) return launch3_cells(P, 3, nullptr, cand, nullptr, s);
   hipLaunchKernelGGL(k_cells<M_EXPORT_CAND>, dim3(blocks_for(P.n_cell, kWavesPerBlock)),
                      dim3(256), 0, s, P, (const float*)nullptr, cand, (float*)nullptr);
   return hipGetLastError();

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GmmspGridInfo, GmmspParams, THETA_ROW, check, lib
+from ._lib import GmmspGridInfo, GmmspParams, check, lib
 
 
 def make_params(W: int, H: int, K: int = 0, vx: int = 0, vy: int = 0, eps_s: float = 2.0,
@@ -39,7 +39,7 @@ class GMMSP:
 
     def __init__(self, sizes: Sequence[tuple], K=None, v=None, eps_s: float = 2.0,
                  eps_c: float = 8.0, lam: float = 8.0, n_min: float = 1e-3,
-                 device="cuda"):
+                 device="cuda", cov_mode: int = 0):
         n = len(sizes)
         # a list gives one value per image; a (vx, vy) tuple is one spacing for all
         Ks = K if isinstance(K, list) else [K] * n
@@ -48,8 +48,10 @@ class GMMSP:
         for b, (W, H) in enumerate(sizes):
             vb = vs[b]
             vx, vy = (vb if isinstance(vb, (list, tuple)) else (vb, vb)) if vb else (0, 0)
-            arr[b] = make_params(W, H, Ks[b] or 0, vx, vy, eps_s, eps_c, lam, 0, n_min)
+            arr[b] = make_params(W, H, Ks[b] or 0, vx, vy, eps_s, eps_c, lam, cov_mode, n_min)
         self.params = arr
+        self.cov_mode = cov_mode
+        self.theta_row = _lib.THETA_ROW3 if cov_mode == 1 else _lib.THETA_ROW
         self.n_images = n
         self.device = torch.device(device)
         nbytes = c_size_t(0)
@@ -102,19 +104,19 @@ class GMMSP:
         """theta rows (n_superpixels, 13): numpy (host) or a float64 device tensor."""
         if isinstance(rows, torch.Tensor) and rows.device.type == "cuda":
             if rows.dtype != torch.float64 or not rows.is_contiguous() or \
-                    rows.shape != (self.n_superpixels, THETA_ROW):
-                raise ValueError("theta must be a contiguous (n_sp, 13) float64 tensor")
+                    rows.shape != (self.n_superpixels, self.theta_row):
+                raise ValueError(f"theta must be a contiguous (n_sp, {self.theta_row}) float64 tensor")
             check(lib().gmmsp_set_params_dev(self.handle, c_void_p(_ptr(rows)),
                                              c_void_p(self._stream())))
             return
         a = np.ascontiguousarray(np.asarray(rows, dtype=np.float64))
-        if a.shape != (self.n_superpixels, THETA_ROW):
-            raise ValueError("theta must have shape (n_superpixels, 13)")
+        if a.shape != (self.n_superpixels, self.theta_row):
+            raise ValueError(f"theta must have shape (n_superpixels, {self.theta_row})")
         check(lib().gmmsp_set_params(self.handle, c_void_p(a.ctypes.data),
                                      c_void_p(self._stream())))
 
     def get_params(self) -> np.ndarray:
-        out = np.empty((self.n_superpixels, THETA_ROW), dtype=np.float64)
+        out = np.empty((self.n_superpixels, self.theta_row), dtype=np.float64)
         check(lib().gmmsp_get_params(self.handle, c_void_p(out.ctypes.data),
                                      c_void_p(self._stream())))
         return out
