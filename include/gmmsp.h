@@ -341,6 +341,17 @@ int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_
                   const int32_t* n_sp_host, const int32_t* n_gt_host, void* ws_dev,
                   size_t ws_bytes, double* out_host, int64_t* sums_host, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Colour front end: the method runs in CIELAB (Sec. IV); this converts 8-bit
+ * sRGB (IEC 61966-2-1 transfer function, sRGB primaries, D65 white) to CIE
+ * 1976 L*a*b* relative to D65 (2-degree observer), in float32.
+ * rgb_dev: n_pixels x 3 uint8 (R, G, B interleaved), 4-byte aligned;
+ * lab_dev: n_pixels x 3 float32 (L, a, b interleaved, the layout every entry
+ * point above reads), 16-byte aligned.  Needs no handle.  Errors: E_INVAL for
+ * null or misaligned pointers or n_pixels < 0.
+ * ------------------------------------------------------------------------ */
+int gmmsp_srgb8_to_lab(const uint8_t* rgb_dev, int64_t n_pixels, float* lab_dev, void* stream);
+
 const char* gmmsp_last_error(void);
 
 #ifdef __cplusplus

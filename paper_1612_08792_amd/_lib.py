@@ -74,6 +74,7 @@ _SIGS = {
     "gmmsp_ws_read": (c_int, [c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gmmsp_ws_write": (c_int, [c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gmmsp_conn_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
+    "gmmsp_srgb8_to_lab": (c_int, [c_void_p, c_int64, c_void_p, c_void_p]),
     "gmmsp_metrics_workspace_bytes": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_size_t)]),
     "gmmsp_metrics": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_size_t, c_void_p, c_void_p, c_void_p]),

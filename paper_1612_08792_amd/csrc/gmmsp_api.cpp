@@ -1136,4 +1136,19 @@ int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_
   return GMMSP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Colour front end
+// ---------------------------------------------------------------------------
+
+int gmmsp_srgb8_to_lab(const uint8_t* rgb_dev, int64_t n_pixels, float* lab_dev, void* stream) {
+  if (!rgb_dev || !lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (n_pixels < 0) return fail(GMMSP_E_INVAL, "n_pixels < 0");
+  if (((uintptr_t)rgb_dev) & 3) return fail(GMMSP_E_INVAL, "rgb_dev must be 4-byte aligned");
+  if (((uintptr_t)lab_dev) & 15) return fail(GMMSP_E_INVAL, "lab_dev must be 16-byte aligned");
+  if (n_pixels == 0) return GMMSP_OK;
+  hipError_t e = launch_srgb8_to_lab(rgb_dev, n_pixels, lab_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_srgb8_to_lab");
+  return GMMSP_OK;
+}
+
 }  // extern "C"

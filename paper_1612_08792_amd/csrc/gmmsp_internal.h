@@ -154,6 +154,9 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
                              int n_seg, const float* lab, int compact, int32_t* out,
                              hipStream_t s);
 
+// Colour front end (gmmsp_color.hip).
+hipError_t launch_srgb8_to_lab(const uint8_t* rgb, int64_t n, float* lab, hipStream_t s);
+
 // Accuracy measures (gmmsp_metrics.hip).
 int metrics_max_blocks(int max_pixels);
 hipError_t metrics_launch(const DevPtrs& P, int max_pixels, const int32_t* sp, const int32_t* gt,

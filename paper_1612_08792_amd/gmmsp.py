@@ -30,6 +30,18 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def srgb8_to_lab(rgb: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """8-bit sRGB (..., 3) uint8 on the GPU -> CIELAB (..., 3) float32 (D65)."""
+    if rgb.dtype != torch.uint8 or not rgb.is_contiguous() or rgb.shape[-1] != 3 or not rgb.is_cuda:
+        raise ValueError("rgb must be a contiguous (..., 3) uint8 tensor on the GPU")
+    if out is None:
+        out = torch.empty(rgb.shape, dtype=torch.float32, device=rgb.device)
+    s = torch.cuda.current_stream(rgb.device).cuda_stream
+    check(lib().gmmsp_srgb8_to_lab(c_void_p(_ptr(rgb)), rgb.numel() // 3, c_void_p(_ptr(out)),
+                                   c_void_p(s)))
+    return out
+
+
 class GMMSP:
     """A batch of images (one image is a batch of one) bound to a workspace.
 

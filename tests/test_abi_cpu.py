@@ -133,3 +133,12 @@ def test_metrics_rejects_bad_arguments_before_any_device_work():
     p = c_void_p(0x1000)
     assert L.gmmsp_metrics_workspace_bytes(None, None, p, byref(c_size_t(0))) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_metrics(None, p, p, None, p, p, 1 << 20, p, None, None) == _lib.GMMSP_E_INVAL
+
+
+def test_colour_front_end_rejects_bad_arguments():
+    L = _lib.lib()
+    assert L.gmmsp_srgb8_to_lab(None, 4, c_void_p(0x1000), None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_srgb8_to_lab(c_void_p(0x1001), 4, c_void_p(0x1000), None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_srgb8_to_lab(c_void_p(0x1000), 4, c_void_p(0x1004), None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_srgb8_to_lab(c_void_p(0x1000), -1, c_void_p(0x1000), None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_srgb8_to_lab(c_void_p(0x1000), 0, c_void_p(0x1000), None) == 0
