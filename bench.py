@@ -71,7 +71,8 @@ def load_or_train_weights(dev):
         return warmstart.load(path, dev)
     log("no trained warm-start weights: training on the 481x321 set first")
     import synth
-    ims = [synth.config4_image(10000 + i, dev) for i in range(4096)]
+    ims = [synth.voronoi_lab(481, 321, 40, train_warmstart.TRAIN_SIGMA, 10000 + i, 400, dev)
+           for i in range(4096)]
     params, _ = warmstart.train(ims, dev, epochs=200, batch_images=64, lr=2e-3,
                                 target_passes=train_warmstart.TARGET_PASSES)
     return params

@@ -2,10 +2,11 @@
 
     python -m paper_1612_08792_amd.train_warmstart [--images 4096] [--out PATH]
 
-Training set: synthetic 481x321 Voronoi-Lab images (40 regions, sigma 3,
-K = 400) with seeds 10000.., targets = the parameters of plain EM after 24
-passes (produced by the library on the GPU).  Held-out set: seeds 20000..
-(256 images).  Writes the weights (.npz) and an evaluation summary (.json):
+Training set: synthetic 481x321 Voronoi-Lab images (40 regions, K = 400,
+noise sigma drawn per image from U[1, 6] as in the 4K workload) with seeds
+10000.., targets = the parameters of plain EM after 24 passes (produced by
+the library on the GPU).  Held-out set: seeds 20000.. (256 images, the
+sigma-3 law of the 481x321 workload).  Writes the weights (.npz) and an evaluation summary (.json):
 passes of warm-started and plain EM to the plain-EM log-likelihood within 1e-4
 relative, passes to the 1e-5 relative-change stop rule, and the final
 log-likelihoods."""
@@ -32,6 +33,7 @@ from paper_1612_08792_amd.gmmsp import GMMSP  # noqa: E402
 # log-scales are not predictable from the inputs and are left at lambda^2)
 MASK = 0b0001111111
 TARGET_PASSES = 24
+TRAIN_SIGMA = (1.0, 6.0)
 DEFAULT_OUT = os.path.join(warmstart.WEIGHTS_DIR, "ws_481x321.npz")
 
 
@@ -85,7 +87,8 @@ def main():
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ims = [synth.config4_image(10000 + i, dev) for i in range(args.images)]
+    ims = [synth.voronoi_lab(481, 321, 40, TRAIN_SIGMA, 10000 + i, 400, dev)
+           for i in range(args.images)]
     log(f"generated {len(ims)} training images in {time.time() - t0:.1f} s")
     params, info = warmstart.train(ims, dev, epochs=args.epochs, batch_images=args.batch_images,
                                    lr=args.lr, target_passes=TARGET_PASSES,
@@ -95,7 +98,7 @@ def main():
     ev = evaluate(params, dev)
     log(json.dumps(ev))
     info.update(target_passes=TARGET_PASSES, epochs=args.epochs, batch_images=args.batch_images,
-                lr=args.lr, mask=MASK)
+                lr=args.lr, mask=MASK, train_sigma=list(TRAIN_SIGMA))
     warmstart.save(params, args.out, info)
     with open(os.path.splitext(args.out)[0] + "_eval.json", "w") as f:
         json.dump(dict(training={k: v for k, v in info.items() if k != "losses"},
