@@ -104,11 +104,19 @@ def cpu_baseline(lab_img, W, H, K, iters_mean):
     t_e = t2 - t1
     npx = W * H
     t_conv = (t1 - t0) + t_pass * iters_mean + t_e
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {
         "value": round(npx / t_conv / 1e6, 4),
         "unit": "Mpix/s",
         "cores": max(1, int(round(cpu_s / wall))),
         "kind": "oracle",
+        "cpu_model": model,
+        "host_cores_available": len(os.sched_getaffinity(0)),
         "sample": (f"FP64 oracle, one EM pass (E-step {t_e:.1f} s + M-step {t3 - t2:.1f} s) "
                    f"plus set-up {t1 - t0:.1f} s on image 0 ({W}x{H}, K={g.K}); to-convergence "
                    f"time extrapolated to the GPU's mean {iters_mean:.1f} passes + 1 labelling "
