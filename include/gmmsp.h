@@ -8,7 +8,10 @@
  * (Eqs. UpdateMu, UpdateSigS, UpdateSigC) with shape control (Eqs. eigdecs to
  * eigdecrc), the log-likelihood L(theta) (Eq. ftheta), and the final labelling
  * (Eq. obtLi).  It handles a batch of images of different sizes in one set of
- * launches; one image is a batch of one.
+ * launches; one image is a batch of one.  Around the EM: a learned warm start
+ * for theta^0 (gmmsp_ws_*), the connectivity post-processing that ends
+ * Algorithm 1 (gmmsp_connectivity), the accuracy measures of Sec. IV
+ * (gmmsp_metrics) and an sRGB to CIELAB front end (gmmsp_srgb8_to_lab).
  *
  * Conventions shared by every entry point
  *   - Image data: interleaved float32 CIELAB (L, a, b) per pixel, row-major,
