@@ -6,6 +6,7 @@ the one module that both the CPU oracle side and the HIP side read from.
 from .voronoi_lab import (  # noqa: F401
     VoronoiImage,
     voronoi_lab,
+    voronoi_srgb8,
     config1_image,
     config2_image,
     config3_batch,

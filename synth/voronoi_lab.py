@@ -93,6 +93,33 @@ def voronoi_lab(W: int, H: int, n_regions: int, sigma, seed: int, K: int,
     return VoronoiImage(lab=lab, regions=reg, W=W, H=H, K=K, seed=seed, sigma=sig)
 
 
+def voronoi_srgb8(W: int, H: int, n_regions: int, sigma, seed: int,
+                  device="cpu") -> tuple[torch.Tensor, torch.Tensor]:
+    """The same Voronoi law drawn directly as 8-bit sRGB (for the colour front
+    end): per region a colour c0 ~ U[20, 235]^3 and slopes ~ U[-0.05, 0.05]
+    per px, N(0, sigma^2) noise, rounded and clipped to [0, 255].  Returns
+    ((H, W, 3) uint8, (H, W) int32 region ids)."""
+    rng = np.random.default_rng(seed)
+    n = max(1, int(n_regions))
+    sx = rng.uniform(0.0, W, n)
+    sy = rng.uniform(0.0, H, n)
+    c0 = rng.uniform(20.0, 235.0, (n, 3))
+    g = rng.uniform(-0.05, 0.05, (n, 3, 2))
+    sig = float(rng.uniform(sigma[0], sigma[1])) if isinstance(sigma, (tuple, list)) else float(sigma)
+    noise = rng.standard_normal((H, W, 3))
+    dev = torch.device(device)
+    reg = _nearest_site(W, H, sx, sy, dev)
+    regl = reg.long()
+    tc = torch.from_numpy(c0).to(dev)
+    tg = torch.from_numpy(g).to(dev)
+    relx = torch.arange(W, device=dev, dtype=torch.float64)[None, :] - torch.from_numpy(sx).to(dev)[regl]
+    rely = torch.arange(H, device=dev, dtype=torch.float64)[:, None] - torch.from_numpy(sy).to(dev)[regl]
+    col = tc[regl] + tg[regl][..., 0] * relx[..., None] + tg[regl][..., 1] * rely[..., None]
+    col = col + sig * torch.from_numpy(noise).to(dev)
+    rgb = torch.clamp(torch.round(col), 0, 255).to(torch.uint8).contiguous()
+    return rgb, reg
+
+
 # ---------------------------------------------------------------------------
 # The five workloads (sizes and seeds of the benchmark configurations)
 # ---------------------------------------------------------------------------

@@ -270,3 +270,28 @@ def test_4k_sampled_one_step(dev):
         rows4[j] = th4[k]
     e = assert_theta_close(rows4, want4, 1e-5, what="4K one step")
     say("4K one-step errors", e)
+
+
+# ---------------------------------------------------------------------------
+# seeded random shapes: grid sizes, remainders and K drawn at random
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(8))
+def test_random_shapes_match_oracle(dev, seed):
+    rng = np.random.default_rng(1000 + seed)
+    while True:                                       # draw until the seed grid fits the image
+        W, H = int(rng.integers(9, 140)), int(rng.integers(9, 110))
+        K = int(rng.integers(1, max(2, (W * H) // 40)))
+        try:
+            g = O.make_grid(W, H, K=K)
+            break
+        except ValueError:
+            continue
+    im = synth.voronoi_lab(W, H, int(rng.integers(1, 12)), float(rng.uniform(1, 6)), seed, K)
+    ref = O.run_em(im.lab.numpy(), g, max_iters=3)
+    out = run_gpu(im, dev, 3, K=K)
+    say(f"random shape {W}x{H} K={K} -> v={g.vx}, {g.nx}x{g.ny}")
+    assert_theta_close(out["theta"], O.theta_to_rows(ref["theta"]), 1e-3, what=f"{W}x{H} K={K}")
+    Ro = oracle_slots(g, ref["cand"], ref["R"])
+    assert np.abs(out["R"] - Ro).max() <= 1e-4
+    agree, _ = label_agreement(out["labels"], ref["labels"].reshape(-1), oracle_margin(ref["R"]))
+    assert agree >= 0.999
