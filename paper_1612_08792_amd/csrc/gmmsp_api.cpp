@@ -953,7 +953,7 @@ ConnSizes conn_sizes(const gmmsp_handle* h) {
   const size_t n = (size_t)h->n_pix;
   z.pix = align256(sizeof(int) * n);
   z.bsum = align256(sizeof(int) * (gmmsp::conn_scan_blocks((int64_t)n) + 1));
-  z.counts = align256(sizeof(int) * (4 * (size_t)h->n_img + 1));
+  z.counts = align256(sizeof(int) * (4 * (size_t)h->n_img + 2));
   z.seg = z.pix;  // at most one segment per pixel
   z.colsum = align256(sizeof(unsigned long long) * 3 * n);
   z.total = 3 * z.pix + z.bsum + z.counts + 13 * z.seg + z.colsum;
@@ -988,6 +988,7 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
   C.bsum = (int*)take(z.bsum);
   C.counts = (int*)take(z.counts);
   C.total = C.counts + 4 * h->n_img;
+  C.n_big = C.total + 1;
   int** seg[13] = {&C.seg_root, &C.seg_img, &C.size0, &C.size, &C.ccnt, &C.coff, &C.cursor,
                    &C.list, &C.poff, &C.cpar, &C.mpar, &C.next, &C.tail};
   for (int i = 0; i < 13; ++i) *seg[i] = (int*)take(z.seg);

@@ -42,7 +42,8 @@ namespace gmmsp {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kScanBlock = 1024;  // elements per block of the scan (4 per thread)
+constexpr int kScanPer = 16;                // elements per thread of the scan
+constexpr int kScanBlock = kScanPer * 256;  // elements per block of the scan
 
 __device__ __forceinline__ int ld_acq(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -178,19 +179,24 @@ __global__ __launch_bounds__(kT) void k_cc_tile(const ImgDesc* img, const int32_
   }
 }
 
-// joins across tile borders: left edges and top edges of the tiles
-__global__ __launch_bounds__(kT) void k_cc_border(const ImgDesc* img, const int32_t* labels,
+// joins across tile borders: one 64-thread block per tile, threads 0..31 on
+// its left edge, 32..63 on its top edge
+__global__ __launch_bounds__(64) void k_cc_border(const ImgDesc* img, const int32_t* labels,
                                                   int* par) {
-  int b, j, W, H;
-  int64_t off;
-  if (!img_pixel(img, b, j, W, H, off)) return;
-  const int x = j % W, y = j / W;
-  const bool left = x > 0 && x % kTile == 0, top = y > 0 && y % kTile == 0;
-  if (!left && !top) return;
-  const int i = (int)(off + j);
-  const int32_t l = labels[i];
-  if (left && labels[i - 1] == l) uf_unite(par, i, i - 1);
-  if (top && labels[i - W] == l) uf_unite(par, i, i - W);
+  const int b = blockIdx.y;
+  const ImgDesc& I = img[b];
+  const int W = I.W, H = I.H;
+  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  if ((int)blockIdx.x >= tiles_x * tiles_y) return;
+  const int x0 = (blockIdx.x % tiles_x) * kTile, y0 = (blockIdx.x / tiles_x) * kTile;
+  const int t = threadIdx.x;
+  const bool left = t < kTile;
+  const int x = left ? x0 : x0 + (t - kTile), y = left ? y0 + t : y0;
+  if (x >= W || y >= H) return;
+  if (left ? x0 == 0 : y0 == 0) return;
+  const int i = (int)(I.pix_off + (int64_t)y * W + x);
+  const int j = left ? i - 1 : i - W;
+  if (labels[i] == labels[j]) uf_unite(par, i, j);
 }
 
 __global__ __launch_bounds__(kT) void k_cc_flatten(const ImgDesc* img, int* par, int* flag) {
@@ -207,14 +213,25 @@ __global__ __launch_bounds__(kT) void k_cc_flatten(const ImgDesc* img, int* par,
 
 __global__ __launch_bounds__(kT) void k_scan_blocks(int* a, int n, int* bsum) {
   __shared__ int sh[kT];
-  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
-  int v[4];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  const bool whole = base + kScanPer <= n;
+  if (whole) {  // a is 256-byte aligned: four 16-byte loads
+#pragma unroll
+    for (int k = 0; k < kScanPer / 4; ++k) {
+      const int4 w = reinterpret_cast<const int4*>(a + base)[k];
+      v[4 * k] = w.x;
+      v[4 * k + 1] = w.y;
+      v[4 * k + 2] = w.z;
+      v[4 * k + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = base + k < n ? a[base + k] : 0;
+  }
   int t = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = base + k < n ? a[base + k] : 0;
-    t += v[k];
-  }
+  for (int k = 0; k < kScanPer; ++k) t += v[k];
   sh[threadIdx.x] = t;
   __syncthreads();
   // Hillis-Steele inclusive scan of the per-thread totals
@@ -226,9 +243,20 @@ __global__ __launch_bounds__(kT) void k_scan_blocks(int* a, int n, int* bsum) {
   }
   int run = sh[threadIdx.x] - t;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < n) a[base + k] = run;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int e = run;
     run += v[k];
+    v[k] = e;
+  }
+  if (whole) {
+#pragma unroll
+    for (int k = 0; k < kScanPer / 4; ++k)
+      reinterpret_cast<int4*>(a + base)[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2],
+                                                       v[4 * k + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (base + k < n) a[base + k] = v[k];
   }
   if (threadIdx.x == kT - 1) bsum[blockIdx.x] = sh[kT - 1];
 }
@@ -259,11 +287,13 @@ __global__ __launch_bounds__(kT) void k_scan_totals(int* bsum, int nb, int* tota
 }
 
 __global__ __launch_bounds__(kT) void k_scan_add(int* a, int n, const int* bsum) {
-  const int base = blockIdx.x * kScanBlock + threadIdx.x * 4;
   const int add = bsum[blockIdx.x];
+  // consecutive threads on consecutive elements
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (base + k < n) a[base + k] += add;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = blockIdx.x * kScanBlock + k * kT + threadIdx.x;
+    if (i < n) a[i] += add;
+  }
 }
 
 // ---- segments ---------------------------------------------------------------
@@ -443,19 +473,51 @@ __device__ void sift_down(int* v, const int* size0, int root, int n) {
   }
 }
 
-// The merge, one thread per cluster: sort its sources by (size, id), then
-// visit them in that order.
-__global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, const int* seg_img,
-                                              const int* seg_root, const int* size0,
-                                              const int* cpar, const int* ccnt, const int* coff,
-                                              int* list, const int* poff, const int* plist,
-                                              const int* segid, const double* mean, int* size,
-                                              int* mpar, int* next, int* tail) {
-  const int r = blockIdx.x * kT + threadIdx.x;
-  if (r >= n_seg || !is_small(img, seg_img, size0, r) || cpar[r] != r) return;
+// The colour-nearest neighbour among the 4-neighbours of pixel j (image-local
+// index) for segment s: updates (best, bd); ties to the smaller id.
+__device__ __forceinline__ void scan_pixel(int j, int W, int H, int off, int s, const double* ms,
+                                           const int* segid, const int* mpar, const double* mean,
+                                           int& best, double& bd) {
+  const int x = j % W, y = j / W;
+  int nb[4];
+  int k = 0;
+  if (y > 0) nb[k++] = j - W;
+  if (y + 1 < H) nb[k++] = j + W;
+  if (x > 0) nb[k++] = j - 1;
+  if (x + 1 < W) nb[k++] = j + 1;
+  for (int e = 0; e < k; ++e) {
+    const int t = m_find(mpar, segid[off + nb[e]]);
+    if (t == s) continue;
+    const double d = colour_dist2(ms, mean + 3 * (int64_t)t);
+    if (best < 0 || d < bd || (d == bd && t < best)) {
+      best = t;
+      bd = d;
+    }
+  }
+}
+
+// merge s into best: size transfer and, inside the cluster, the hand-over of
+// the member chain
+__device__ __forceinline__ void merge_into(const ImgDesc* img, const int* seg_img, const int* size0,
+                                           int s, int best, int* size, int* mpar, int* next,
+                                           int* tail) {
+  mpar[s] = best;
+  atomicAdd(size + best, size[s]);
+  size[s] = 0;
+  if (is_small(img, seg_img, size0, best)) {
+    next[tail[best]] = s;
+    tail[best] = tail[s];
+  }
+}
+
+// The procedure on one cluster, one thread: heap sort of its sources by
+// (size, id), then the visits in that order.
+__device__ void merge_cluster(const ImgDesc* img, int r, const int* seg_img, const int* size0,
+                              const int* ccnt, const int* coff, int* list, const int* poff,
+                              const int* plist, const int* segid, const double* mean, int* size,
+                              int* mpar, int* next, int* tail) {
   const int n = ccnt[r];
   int* v = list + coff[r];
-  // heap sort, ascending by (size, id)
   for (int k = n / 2 - 1; k >= 0; --k) sift_down(v, size0, k, n);
   for (int e = n - 1; e > 0; --e) {
     const int t = v[0];
@@ -475,36 +537,116 @@ __global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, con
     double bd = 0.0;
     for (int m = s; m >= 0; m = next[m]) {
       const int p0 = poff[m], np = size0[m];
-      for (int u = 0; u < np; ++u) {
-        const int j = plist[p0 + u] - off;
-        const int x = j % W, y = j / W;
-        int nb[4];
-        int k = 0;
-        if (y > 0) nb[k++] = j - W;
-        if (y + 1 < H) nb[k++] = j + W;
-        if (x > 0) nb[k++] = j - 1;
-        if (x + 1 < W) nb[k++] = j + 1;
-        for (int e = 0; e < k; ++e) {
-          const int t = m_find(mpar, segid[off + nb[e]]);
-          if (t == s) continue;
-          const double d = colour_dist2(ms, mean + 3 * (int64_t)t);
-          if (best < 0 || d < bd || (d == bd && t < best)) {
-            best = t;
-            bd = d;
+      for (int u = 0; u < np; ++u)
+        scan_pixel(plist[p0 + u] - off, W, H, off, s, ms, segid, mpar, mean, best, bd);
+    }
+    if (best >= 0) merge_into(img, seg_img, size0, s, best, size, mpar, next, tail);
+  }
+}
+
+// clusters of at most kBig sources run here, one thread each; larger ones are
+// listed for k_merge_big
+constexpr int kBig = 16;
+
+__global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, const int* seg_img,
+                                              const int* size0, const int* cpar, const int* ccnt,
+                                              const int* coff, int* list, const int* poff,
+                                              const int* plist, const int* segid,
+                                              const double* mean, int* size, int* mpar, int* next,
+                                              int* tail, int* big, int* n_big) {
+  const int r = blockIdx.x * kT + threadIdx.x;
+  if (r >= n_seg || !is_small(img, seg_img, size0, r) || cpar[r] != r) return;
+  if (ccnt[r] > kBig) {
+    big[atomicAdd(n_big, 1)] = r;
+    return;
+  }
+  merge_cluster(img, r, seg_img, size0, ccnt, coff, list, poff, plist, segid, mean, size, mpar,
+                next, tail);
+}
+
+// Large clusters, one wave each: the sources sorted by (size, id) with a
+// bitonic sort in LDS, then visited in order with the wave's lanes sharing the
+// pixels of the source and a butterfly for the nearest neighbour.  The state
+// one visit writes (lane 0) is made visible to the wave before the next visit.
+constexpr int kSortCap = 1024;
+constexpr int kMergeWaves = 4;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kMergeWaves) void k_merge_big(
+    const ImgDesc* img, const int* seg_img, const int* size0, const int* ccnt, const int* coff,
+    int* list, const int* poff, const int* plist, const int* segid, const double* mean, int* size,
+    int* mpar, int* next, int* tail, const int* big, const int* n_big) {
+  __shared__ unsigned long long keys[kMergeWaves][kSortCap];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned long long* kw = keys[wv];
+  const int nbig = *n_big;
+  for (int c = blockIdx.x * kMergeWaves + wv; c < nbig; c += gridDim.x * kMergeWaves) {
+    const int r = big[c];
+    const int n = ccnt[r];
+    if (n > kSortCap) {  // too large for the LDS sort: one lane runs it all
+      if (lane == 0)
+        merge_cluster(img, r, seg_img, size0, ccnt, coff, list, poff, plist, segid, mean, size,
+                      mpar, next, tail);
+      continue;
+    }
+    const int* v = list + coff[r];
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = lane; i < P; i += 64)
+      kw[i] = i < n ? ((unsigned long long)size0[v[i]] << 32) | (unsigned)v[i] : ~0ull;
+    wave_sync_lds();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < P; i += 64) {
+          const int l = i ^ j;
+          if (l > i) {
+            const unsigned long long a = kw[i], b = kw[l];
+            if ((a > b) == ((i & k) == 0)) {
+              kw[i] = b;
+              kw[l] = a;
+            }
           }
         }
+        wave_sync_lds();
       }
     }
-    if (best < 0) continue;
-    mpar[s] = best;
-    atomicAdd(size + best, size[s]);
-    size[s] = 0;
-    if (is_small(img, seg_img, size0, best)) {  // same cluster: hand over the pixels
-      next[tail[best]] = s;
-      tail[best] = tail[s];
+    const ImgDesc& I = img[seg_img[r]];
+    const int W = I.W, H = I.H;
+    const int off = (int)I.pix_off;
+    const int64_t desired = (int64_t)I.vx * I.vy;
+    for (int q = 0; q < n; ++q) {
+      const int s = (int)(unsigned)(kw[q] & 0xFFFFFFFFull);
+      if (4LL * size[s] >= desired) continue;
+      const double* ms = mean + 3 * (int64_t)s;
+      int best = -1;
+      double bd = 0.0;
+      for (int m = s; m >= 0; m = next[m]) {
+        const int p0 = poff[m], np = size0[m];
+        for (int u = lane; u < np; u += 64)
+          scan_pixel(plist[p0 + u] - off, W, H, off, s, ms, segid, mpar, mean, best, bd);
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double od = __shfl_xor(bd, o, 64);
+        const int ob = __shfl_xor(best, o, 64);
+        if (ob >= 0 && (best < 0 || od < bd || (od == bd && ob < best))) {
+          best = ob;
+          bd = od;
+        }
+      }
+      if (best < 0) continue;  // every lane holds the same result
+      if (lane == 0) merge_into(img, seg_img, size0, s, best, size, mpar, next, tail);
+      // lane 0's writes, seen by every lane's reads of the next visit
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
-  (void)seg_root;
 }
 
 __global__ __launch_bounds__(kT) void k_root_flags(int n_seg, const int* mpar, int* flag) {
@@ -585,7 +727,7 @@ hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_i
                                   hipStream_t s) {
   const dim3 g(blocks(max_pixels), n_img);
   hipLaunchKernelGGL(k_cc_tile, dim3(max_tiles, n_img), dim3(kT), 0, s, img, labels, C.par);
-  hipLaunchKernelGGL(k_cc_border, g, dim3(kT), 0, s, img, labels, C.par);
+  hipLaunchKernelGGL(k_cc_border, dim3(max_tiles, n_img), dim3(64), 0, s, img, labels, C.par);
   hipLaunchKernelGGL(k_cc_flatten, g, dim3(kT), 0, s, img, C.par, C.scan);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -620,9 +762,16 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
   // the pixel union-find array is free now: it holds the sources' pixel lists
   hipLaunchKernelGGL(k_px_fill, g, dim3(kT), 0, s, img, C.segid, C.seg_img, C.size0, C.poff,
                      C.cursor, C.par);
-  hipLaunchKernelGGL(k_merge, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.seg_root,
-                     C.size0, C.cpar, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
-                     reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail);
+  // the pixel-flag scan array is free until the final ranks: it lists the large clusters
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kT), 0, s, 1, C.n_big);
+  hipLaunchKernelGGL(k_merge, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.cpar,
+                     C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
+                     reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail,
+                     C.scan, C.n_big);
+  hipLaunchKernelGGL(k_merge_big, dim3(1024), dim3(64 * kMergeWaves), 0, s, img, C.seg_img,
+                     C.size0, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
+                     reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail,
+                     C.scan, C.n_big);
   // the pixel-flag scan is free now: it ranks the final segments
   hipLaunchKernelGGL(k_root_flags, dim3(gs), dim3(kT), 0, s, n_seg, C.mpar, C.scan);
   e = scan(C.scan, n_seg, C.bsum, C.total, s);

@@ -140,6 +140,7 @@ struct ConnPtrs {
   int* scan;                // root flags, then their exclusive scan
   int* bsum;                // scan block totals
   int* total;               // scan total (the number of segments after the first scan)
+  int* n_big;               // number of clusters handled one wave each
   int* counts;              // [n_img][4]: segments, small, merged, (unused)
   int *seg_root, *seg_img, *size0, *size, *ccnt, *coff, *cursor, *list, *poff;
   int *cpar, *mpar, *next, *tail;
