@@ -945,18 +945,27 @@ int gmmsp_ws_write(gmmsp_handle* h, int32_t which, const void* host, size_t byte
 namespace {
 
 struct ConnSizes {
-  size_t pix, bsum, counts, seg, colsum, total;
+  size_t pix, bsum, counts, seg, colsum, side, total;
+  int max_pix, max_tiles, max_w, max_h;
 };
 
 ConnSizes conn_sizes(const gmmsp_handle* h) {
   ConnSizes z;
+  z.max_pix = z.max_tiles = z.max_w = z.max_h = 0;
+  for (const ImgDesc& I : h->img) {
+    z.max_pix = std::max(z.max_pix, I.W * I.H);
+    z.max_w = std::max(z.max_w, I.W);
+    z.max_h = std::max(z.max_h, I.H);
+    z.max_tiles = std::max(z.max_tiles, (int)gmmsp::conn_tiles(I.W, I.H));
+  }
   const size_t n = (size_t)h->n_pix;
   z.pix = align256(sizeof(int) * n);
   z.bsum = align256(sizeof(int) * (gmmsp::conn_scan_blocks((int64_t)n) + 1));
   z.counts = align256(sizeof(int) * (4 * (size_t)h->n_img + 2));
   z.seg = z.pix;  // at most one segment per pixel
   z.colsum = align256(sizeof(unsigned long long) * 3 * n);
-  z.total = 3 * z.pix + z.bsum + z.counts + 13 * z.seg + z.colsum;
+  z.side = align256(sizeof(int) * gmmsp::conn_side_ints(h->n_img, z.max_tiles));
+  z.total = 3 * z.pix + z.bsum + z.counts + 13 * z.seg + z.colsum + z.side;
   return z;
 }
 
@@ -993,11 +1002,8 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
                    &C.list, &C.poff, &C.cpar, &C.mpar, &C.next, &C.tail};
   for (int i = 0; i < 13; ++i) *seg[i] = (int*)take(z.seg);
   C.colsum = (unsigned long long*)take(z.colsum);
-  int max_pix = 0, max_tiles = 0;
-  for (const ImgDesc& I : h->img) {
-    max_pix = std::max(max_pix, I.W * I.H);
-    max_tiles = std::max(max_tiles, (int)conn_tiles(I.W, I.H));
-  }
+  C.side = (int*)take(z.side);
+  const int max_pix = z.max_pix, max_tiles = z.max_tiles;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = conn_launch_components(C, h->P.img, h->n_img, max_pix, max_tiles, labels_dev, s);
   int n_seg = 0;
@@ -1005,7 +1011,8 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity (components)");
   if (n_seg < 1 || n_seg > h->n_pix) return fail(GMMSP_E_STATE, "segment count %d out of range", n_seg);
-  e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, n_seg, lab_dev, compact ? 1 : 0, out_dev, s);
+  e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, z.max_w, z.max_h, n_seg, lab_dev,
+                        compact ? 1 : 0, out_dev, s);
   if (e == hipSuccess && counts_host) {
     std::vector<int> c(4 * (size_t)h->n_img);
     e = hipMemcpyAsync(c.data(), C.counts, sizeof(int) * c.size(), hipMemcpyDeviceToHost, s);

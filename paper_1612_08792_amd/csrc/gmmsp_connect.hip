@@ -115,12 +115,19 @@ __device__ __forceinline__ int m_find(const int* mpar, int t) {
 }
 
 // ---- pixel components ------------------------------------------------------
-// A block labels a 32 x 32 tile in LDS (union-find with LDS atomics, local
-// raster order, which is the global order inside a tile), writes each pixel's
-// tile-local root as a global index, and the tile borders are then joined in
-// global memory.  Roots stay the minimum index of their set throughout.
+// A block labels a 64 x 64 tile in LDS, one tile row per wave at a time:
+// every pixel first points at the head of its horizontal run of equal label
+// (found with a ballot), then each overlap of two equal runs on adjacent rows
+// is joined once, by its first pixel (union-find with LDS atomics, roots the
+// smallest tile-local raster index, which is also the smallest global index).
+// The block writes each pixel's tile root as a global index and keeps the
+// labels and roots of the tile's first and last columns in a side buffer; the
+// tile borders are then joined in global memory from those and from the
+// tiles' first rows.  Roots stay the minimum index of their set throughout.
 
-constexpr int kTile = 32;
+constexpr int kTW = 64, kTH = 64;  // tile of the component labelling
+constexpr int kSide = 4 * kTH;     // first-column labels, roots; last-column labels, roots
+constexpr int kTileWaves = kT / 64;
 
 __device__ int lds_find(int* lp, int x) {
   int y = __hip_atomic_load(lp + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -148,65 +155,153 @@ __device__ void lds_unite(int* lp, int a, int b) {
 }
 
 __global__ __launch_bounds__(kT) void k_cc_tile(const ImgDesc* img, const int32_t* labels,
-                                                int* par) {
-  __shared__ int lp[kTile * kTile];
-  __shared__ int32_t ll[kTile * kTile];
+                                                int* par, int* side, int max_tiles) {
+  __shared__ int lp[kTW * kTH];
+  __shared__ int32_t ll[kTW * kTH];
   const int b = blockIdx.y;
   const ImgDesc& I = img[b];
   const int W = I.W, H = I.H;
-  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
   if ((int)blockIdx.x >= tiles_x * tiles_y) return;  // the whole block
-  const int x0 = (blockIdx.x % tiles_x) * kTile, y0 = (blockIdx.x / tiles_x) * kTile;
+  const int x0 = (blockIdx.x % tiles_x) * kTW, y0 = (blockIdx.x / tiles_x) * kTH;
   const int64_t off = I.pix_off;
-  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
-    const int x = x0 + l % kTile, y = y0 + l / kTile;
-    lp[l] = l;
-    ll[l] = (x < W && y < H) ? labels[off + (int64_t)y * W + x] : 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = x0 + lane;
+  const bool xin = x < W;
+  // labels and run heads (pixels outside the image are runs of their own)
+  for (int ty = wv; ty < kTH; ty += kTileWaves) {
+    const bool in = xin && y0 + ty < H;
+    const int l = ty * kTW + lane;
+    const int32_t lab = in ? labels[off + (int64_t)(y0 + ty) * W + x] : 0;
+    ll[l] = lab;
+    const int32_t left = __shfl_up(lab, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || left != lab || !in);
+    const unsigned long long upto = heads & ((2ull << lane) - 1ull);  // bits 0..lane
+    lp[l] = ty * kTW + 63 - __builtin_clzll(upto);
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
-    const int tx = l % kTile, ty = l / kTile;
-    if (x0 + tx >= W || y0 + ty >= H) continue;
-    if (tx > 0 && ll[l - 1] == ll[l]) lds_unite(lp, l, l - 1);
-    if (ty > 0 && ll[l - kTile] == ll[l]) lds_unite(lp, l, l - kTile);
+  // vertical joins: the first pixel of each overlap of equal runs
+  for (int ty = 1 + wv; ty < kTH; ty += kTileWaves) {
+    if (!xin || y0 + ty >= H) continue;
+    const int l = ty * kTW + lane;
+    const int32_t lab = ll[l];
+    if (ll[l - kTW] != lab) continue;
+    if (lane > 0 && ll[l - 1] == lab && ll[l - kTW - 1] == lab) continue;
+    lds_unite(lp, l, l - kTW);
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < kTile * kTile; l += kT) {
-    const int x = x0 + l % kTile, y = y0 + l / kTile;
-    if (x >= W || y >= H) continue;
+  int* sd = side + ((size_t)b * max_tiles + blockIdx.x) * kSide;
+  const int xl = min(kTW, W - x0) - 1;  // the tile's last column
+  for (int ty = wv; ty < kTH; ty += kTileWaves) {
+    if (!xin || y0 + ty >= H) continue;
+    const int l = ty * kTW + lane;
     const int r = lds_find(lp, l);
-    par[off + (int64_t)y * W + x] = (int)(off + (int64_t)(y0 + r / kTile) * W + x0 + r % kTile);
+    const int g = (int)(off + (int64_t)(y0 + r / kTW) * W + x0 + r % kTW);
+    par[off + (int64_t)(y0 + ty) * W + x] = g;
+    if (lane == 0) {
+      sd[ty] = ll[l];
+      sd[kTH + ty] = g;
+    }
+    if (lane == xl) {
+      sd[2 * kTH + ty] = ll[l];
+      sd[3 * kTH + ty] = g;
+    }
   }
 }
 
-// joins across tile borders: one 64-thread block per tile, threads 0..31 on
-// its left edge, 32..63 on its top edge
-__global__ __launch_bounds__(64) void k_cc_border(const ImgDesc* img, const int32_t* labels,
-                                                  int* par) {
+// Joins across tile borders, one block per tile: wave 0 joins the tile's first
+// row to the row above it, wave 1 its first column to the column on its left
+// (from the side buffer).  As inside the tiles, only the first pixel of each
+// overlap of equal runs along the border joins.
+__global__ __launch_bounds__(128) void k_cc_border(const ImgDesc* img, const int32_t* labels,
+                                                   int* par, const int* side, int max_tiles) {
   const int b = blockIdx.y;
   const ImgDesc& I = img[b];
   const int W = I.W, H = I.H;
-  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+  const int tiles_x = (W + kTW - 1) / kTW, tiles_y = (H + kTH - 1) / kTH;
   if ((int)blockIdx.x >= tiles_x * tiles_y) return;
-  const int x0 = (blockIdx.x % tiles_x) * kTile, y0 = (blockIdx.x / tiles_x) * kTile;
-  const int t = threadIdx.x;
-  const bool left = t < kTile;
-  const int x = left ? x0 : x0 + (t - kTile), y = left ? y0 + t : y0;
-  if (x >= W || y >= H) return;
-  if (left ? x0 == 0 : y0 == 0) return;
-  const int i = (int)(I.pix_off + (int64_t)y * W + x);
-  const int j = left ? i - 1 : i - W;
-  if (labels[i] == labels[j]) uf_unite(par, i, j);
+  const int x0 = (blockIdx.x % tiles_x) * kTW, y0 = (blockIdx.x / tiles_x) * kTH;
+  const int t = threadIdx.x & 63;
+  int32_t a = 0, c = 0;
+  int ra = 0, rc = 0;
+  bool in;
+  if (threadIdx.x < 64) {  // first row against the row above
+    if (y0 == 0) return;
+    in = x0 + t < W;
+    const int64_t i = I.pix_off + (int64_t)y0 * W + x0 + t;
+    if (in) {
+      a = labels[i];
+      c = labels[i - W];
+      ra = ld_acq(par + i);
+      rc = ld_acq(par + i - W);
+    }
+  } else {  // first column against the last column of the tile on the left
+    if (x0 == 0) return;
+    in = y0 + t < H;
+    const int* me = side + ((size_t)b * max_tiles + blockIdx.x) * kSide;
+    const int* lf = me - kSide;
+    if (in) {
+      a = me[t];
+      ra = me[kTH + t];
+      c = lf[2 * kTH + t];
+      rc = lf[3 * kTH + t];
+    }
+  }
+  const int32_t ap = __shfl_up(a, 1, 64), cp = __shfl_up(c, 1, 64);
+  if (!in || a != c) return;
+  if (t > 0 && ap == a && cp == a) return;  // joined through the previous pixel
+  uf_unite(par, ra, rc);
 }
 
-__global__ __launch_bounds__(kT) void k_cc_flatten(const ImgDesc* img, int* par, int* flag) {
-  int b, j, W, H;
-  int64_t off;
-  if (!img_pixel(img, b, j, W, H, off)) return;
-  const int i = (int)(off + j);
-  const int r = uf_find(par, i);
-  par[i] = r;
-  flag[i] = r == i;
+// Segment numbering: the roots of the pixel forest (par[i] == i) in raster
+// order.  Each block of kScanBlock pixels counts its roots and writes each
+// root's rank within the block (at the root only); a root's segment index is
+// that rank plus the exclusive scan of the block counts.
+__global__ __launch_bounds__(kT) void k_root_rank(const int* par, int n, int* rank, int* bsum) {
+  __shared__ int sh[kT];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  if (base + kScanPer <= n) {  // par is 256-byte aligned: four 16-byte loads
+#pragma unroll
+    for (int k = 0; k < kScanPer / 4; ++k) {
+      const int4 w = reinterpret_cast<const int4*>(par + base)[k];
+      v[4 * k] = w.x == base + 4 * k;
+      v[4 * k + 1] = w.y == base + 4 * k + 1;
+      v[4 * k + 2] = w.z == base + 4 * k + 2;
+      v[4 * k + 3] = w.w == base + 4 * k + 3;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = base + k < n && par[base + k] == base + k;
+  }
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) t += v[k];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 1; o < kT; o <<= 1) {
+    const int u = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += u;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - t;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (v[k]) rank[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kT - 1) bsum[blockIdx.x] = sh[kT - 1];
+}
+
+// the root of pixel i (no joins run any more, so plain loads)
+__device__ __forceinline__ int px_root(const int* par, int i) {
+  int x = par[i], y = par[x];
+  while (y != x) {
+    x = y;
+    y = par[x];
+  }
+  return x;
 }
 
 // ---- exclusive scan of int32 (in place), total to *total ---------------------
@@ -261,16 +356,20 @@ __global__ __launch_bounds__(kT) void k_scan_blocks(int* a, int n, int* bsum) {
   if (threadIdx.x == kT - 1) bsum[blockIdx.x] = sh[kT - 1];
 }
 
-// one block: exclusive scan of the nb block totals, in chunks of kT
+// one block: exclusive scan of the nb block totals, in chunks of kScanBlock
 __global__ __launch_bounds__(kT) void k_scan_totals(int* bsum, int nb, int* total) {
   __shared__ int sh[kT];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < nb; c0 += kT) {
-    const int i = c0 + threadIdx.x;
-    const int v = i < nb ? bsum[i] : 0;
-    sh[threadIdx.x] = v;
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kScanBlock) {
+    const int base = c0 + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = base + k < nb ? bsum[base + k] : 0;
+      t += v[k];
+    }
+    sh[threadIdx.x] = t;
     __syncthreads();
     for (int o = 1; o < kT; o <<= 1) {
       const int u = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
@@ -278,10 +377,14 @@ __global__ __launch_bounds__(kT) void k_scan_totals(int* bsum, int nb, int* tota
       sh[threadIdx.x] += u;
       __syncthreads();
     }
-    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += sh[kT - 1];
-    __syncthreads();
+    int run = carry + sh[threadIdx.x] - t;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (base + k < nb) bsum[base + k] = run;
+      run += v[k];
+    }
+    carry += sh[kT - 1];
+    __syncthreads();  // sh is rewritten by the next chunk
   }
   if (threadIdx.x == 0) *total = carry;
 }
@@ -298,22 +401,6 @@ __global__ __launch_bounds__(kT) void k_scan_add(int* a, int n, const int* bsum)
 
 // ---- segments ---------------------------------------------------------------
 
-__global__ __launch_bounds__(kT) void k_seg_assign(const ImgDesc* img, const int* par,
-                                                   const int* scan, int* segid, int* seg_root,
-                                                   int* seg_img) {
-  int b, j, W, H;
-  int64_t off;
-  if (!img_pixel(img, b, j, W, H, off)) return;
-  const int i = (int)(off + j);
-  const int r = par[i];
-  const int s = scan[r];
-  segid[i] = s;
-  if (r == i) {
-    seg_root[s] = i;
-    seg_img[s] = b;
-  }
-}
-
 __global__ __launch_bounds__(kT) void k_seg_zero(int n_seg, int* size0,
                                                  unsigned long long* colsum, int* ccnt) {
   const int s = blockIdx.x * kT + threadIdx.x;
@@ -325,56 +412,107 @@ __global__ __launch_bounds__(kT) void k_seg_zero(int n_seg, int* size0,
   ccnt[s] = 0;
 }
 
-// size and integer colour sums: exact, so the atomics' order does not matter.
-// The 64 consecutive pixels of a wave are first summed per run of equal
-// segment (segmented scan with shuffles); the last lane of each run adds the
-// run's totals.
-__global__ __launch_bounds__(kT) void k_seg_stats(const ImgDesc* img, const float* lab,
-                                                  const int* segid, int* size0,
-                                                  unsigned long long* colsum) {
+// Segment of each pixel, segment roots, and the sizes and integer colour sums
+// (exact, so the order of the additions does not matter).  A block covers a
+// 64 x 16 tile, one row of 64 pixels per wave at a time: each run of equal
+// segment in the row is summed across its lanes, the run totals are gathered
+// per segment in an LDS table, and the block adds each table entry to the
+// segment once.  Entries that do not fit the table go to memory directly.
+constexpr int kSW = 64, kSH = 16;  // tile of the segment statistics
+constexpr int kHash = 128;         // LDS table entries (a power of two)
+
+__device__ __forceinline__ void add_stats(int s, int cnt, const long long (&q)[3], int* size0,
+                                          unsigned long long* colsum) {
+  atomicAdd(size0 + s, cnt);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) atomicAdd(colsum + 3 * s + c, (unsigned long long)q[c]);
+}
+
+__global__ __launch_bounds__(kT) void k_seg_assign(const ImgDesc* img, const float* lab,
+                                                   const int* par, const int* rank,
+                                                   const int* boff, int* segid,
+                                                   int* seg_root, int* seg_img, int* size0,
+                                                   unsigned long long* colsum) {
+  __shared__ int hkey[kHash];
+  __shared__ int hcnt[kHash];
+  __shared__ unsigned long long hsum[3][kHash];
   const int b = blockIdx.y;
   const ImgDesc& I = img[b];
-  const int j = blockIdx.x * kT + threadIdx.x;
-  const int n = I.W * I.H;
-  if ((int)(blockIdx.x * kT) >= n) return;  // whole block beyond the image
-  const bool valid = j < n;
-  const int64_t i = I.pix_off + j;
-  const int lane = threadIdx.x & 63;
-  const int s = valid ? segid[i] : -1;
-  int cnt = valid ? 1 : 0;
-  long long q[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    q[c] = valid ? (long long)rint((double)lab[3 * i + c] * 1048576.0) : 0ll;
-  const int sl = __shfl_up(s, 1, 64);
-  int hp = (lane == 0 || sl != s) ? lane : 0;  // first lane of this lane's run
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(hp, o, 64);
-    if (lane >= o) hp = max(hp, t);
+  const int W = I.W, H = I.H;
+  const int tiles_x = (W + kSW - 1) / kSW;
+  if ((int)blockIdx.x >= tiles_x * ((H + kSH - 1) / kSH)) return;  // the whole block
+  for (int e = threadIdx.x; e < kHash; e += kT) {
+    hkey[e] = -1;
+    hcnt[e] = 0;
+    hsum[0][e] = hsum[1][e] = hsum[2][e] = 0ull;
   }
+  __syncthreads();
+  const int x0 = (blockIdx.x % tiles_x) * kSW, y0 = (blockIdx.x / tiles_x) * kSH;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool xin = x0 + lane < W;
+  for (int ty = wv; ty < kSH; ty += kTileWaves) {
+    const bool in = xin && y0 + ty < H;
+    int s = -1, cnt = 0;
+    long long q[3] = {0, 0, 0};
+    if (in) {
+      const int i = (int)(I.pix_off + (int64_t)(y0 + ty) * W + x0 + lane);
+      const int r = px_root(par, i);
+      s = rank[r] + boff[r / kScanBlock];
+      segid[i] = s;
+      if (r == i) {
+        seg_root[s] = i;
+        seg_img[s] = b;
+      }
+      cnt = 1;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int c0 = __shfl_up(cnt, o, 64);
-    const long long a0 = __shfl_up(q[0], o, 64), a1 = __shfl_up(q[1], o, 64),
-                    a2 = __shfl_up(q[2], o, 64);
-    if (lane - o >= hp) {
-      cnt += c0;
-      q[0] += a0;
-      q[1] += a1;
-      q[2] += a2;
+      for (int c = 0; c < 3; ++c) q[c] = (long long)rint((double)lab[3 * (int64_t)i + c] * 1048576.0);
     }
-  }
-  const int sr = __shfl_down(s, 1, 64);
-  if (valid && (lane == 63 || sr != s)) {
-    atomicAdd(size0 + s, cnt);
+    // runs of equal segment: the head lane of each, then sums within runs
+    const int sl = __shfl_up(s, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || sl != s);
+    const int hp = 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) atomicAdd(colsum + 3 * s + c, (unsigned long long)q[c]);
+    for (int o = 1; o < 64; o <<= 1) {
+      const int c0 = __shfl_up(cnt, o, 64);
+      const long long a0 = __shfl_up(q[0], o, 64), a1 = __shfl_up(q[1], o, 64),
+                      a2 = __shfl_up(q[2], o, 64);
+      if (lane - o >= hp) {
+        cnt += c0;
+        q[0] += a0;
+        q[1] += a1;
+        q[2] += a2;
+      }
+    }
+    const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    if (!in || !last) continue;
+    // the run's totals into the table (open addressing, linear probing)
+    const int h0 = (int)(((unsigned)s * 2654435761u) >> 25);  // top 7 bits: 0 .. kHash - 1
+    bool done = false;
+    for (int p = 0; p < kHash && !done; ++p) {
+      const int e = (h0 + p) & (kHash - 1);
+      const int k = atomicCAS(hkey + e, -1, s);
+      if (k == -1 || k == s) {
+        atomicAdd(hcnt + e, cnt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&hsum[c][e], (unsigned long long)q[c]);
+        done = true;
+      }
+    }
+    if (!done) add_stats(s, cnt, q, size0, colsum);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kHash; e += kT) {
+    const int k = hkey[e];
+    if (k < 0) continue;
+    const long long q[3] = {(long long)hsum[0][e], (long long)hsum[1][e], (long long)hsum[2][e]};
+    add_stats(k, hcnt[e], q, size0, colsum);
   }
 }
 
-// means (in place of the sums), working sizes, parents, chains
-__global__ __launch_bounds__(kT) void k_seg_prep(int n_seg, const int* size0,
+// means (in place of the sums), working sizes, parents, chains; the cluster
+// parent of a large segment is -1, which marks it large from here on
+__global__ __launch_bounds__(kT) void k_seg_prep(const ImgDesc* img, int n_seg,
+                                                 const int* seg_img, const int* size0,
                                                  unsigned long long* colsum, int* size,
                                                  int* mpar, int* cpar, int* next, int* tail) {
   const int s = blockIdx.x * kT + threadIdx.x;
@@ -388,50 +526,41 @@ __global__ __launch_bounds__(kT) void k_seg_prep(int n_seg, const int* size0,
   }
   size[s] = n;
   mpar[s] = s;
-  cpar[s] = s;
+  cpar[s] = is_small(img, seg_img, size0, s) ? s : -1;
   next[s] = -1;
   tail[s] = s;
 }
 
 // clusters: union of 4-adjacent small segments
-__global__ __launch_bounds__(kT) void k_cl_link(const ImgDesc* img, const int* segid,
-                                                const int* seg_img, const int* size0,
-                                                int* cpar) {
+// (a small segment's cluster parent is never negative, a large one's is -1)
+__global__ __launch_bounds__(kT) void k_cl_link(const ImgDesc* img, const int* segid, int* cpar) {
   int b, j, W, H;
   int64_t off;
   if (!img_pixel(img, b, j, W, H, off)) return;
   const int i = (int)(off + j);
   const int s = segid[i];
-  if (!is_small(img, seg_img, size0, s)) return;
   const int x = j % W, y = j / W;
-  if (x > 0) {
-    const int t = segid[i - 1];
-    if (t != s && is_small(img, seg_img, size0, t)) uf_unite(cpar, s, t);
-  }
-  if (y > 0) {
-    const int t = segid[i - W];
-    if (t != s && is_small(img, seg_img, size0, t)) uf_unite(cpar, s, t);
-  }
+  const int tl = x > 0 ? segid[i - 1] : s, tu = y > 0 ? segid[i - W] : s;
+  if ((tl == s && tu == s) || cpar[s] < 0) return;
+  if (tl != s && cpar[tl] >= 0) uf_unite(cpar, s, tl);
+  if (tu != s && cpar[tu] >= 0) uf_unite(cpar, s, tu);
 }
 
-__global__ __launch_bounds__(kT) void k_cl_count(const ImgDesc* img, int n_seg,
-                                                 const int* seg_img, const int* size0, int* cpar,
-                                                 int* ccnt) {
+__global__ __launch_bounds__(kT) void k_cl_count(int n_seg, int* cpar, int* ccnt) {
   const int s = blockIdx.x * kT + threadIdx.x;
-  if (s >= n_seg || !is_small(img, seg_img, size0, s)) return;
+  if (s >= n_seg || cpar[s] < 0) return;
   const int r = uf_find(cpar, s);
   cpar[s] = r;
   atomicAdd(ccnt + r, 1);
 }
 
 // cluster lists (any order) and the sources' pixel-list sizes
-__global__ __launch_bounds__(kT) void k_cl_fill(const ImgDesc* img, int n_seg, const int* seg_img,
-                                                const int* size0, const int* cpar,
+__global__ __launch_bounds__(kT) void k_cl_fill(int n_seg, const int* size0, const int* cpar,
                                                 const int* coff, int* cursor, int* list,
                                                 int* psz) {
   const int s = blockIdx.x * kT + threadIdx.x;
   if (s >= n_seg) return;
-  const bool small = is_small(img, seg_img, size0, s);
+  const bool small = cpar[s] >= 0;
   psz[s] = small ? size0[s] : 0;
   if (!small) return;
   const int r = cpar[s];
@@ -445,14 +574,14 @@ __global__ __launch_bounds__(kT) void k_zero(int n, int* a) {
 }
 
 __global__ __launch_bounds__(kT) void k_px_fill(const ImgDesc* img, const int* segid,
-                                                const int* seg_img, const int* size0,
-                                                const int* poff, int* cursor, int* plist) {
+                                                const int* cpar, const int* poff, int* cursor,
+                                                int* plist) {
   int b, j, W, H;
   int64_t off;
   if (!img_pixel(img, b, j, W, H, off)) return;
   const int i = (int)(off + j);
   const int s = segid[i];
-  if (!is_small(img, seg_img, size0, s)) return;
+  if (cpar[s] < 0) return;
   plist[poff[s] + atomicAdd(cursor + s, 1)] = i;
 }
 
@@ -555,7 +684,7 @@ __global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, con
                                               const double* mean, int* size, int* mpar, int* next,
                                               int* tail, int* big, int* n_big) {
   const int r = blockIdx.x * kT + threadIdx.x;
-  if (r >= n_seg || !is_small(img, seg_img, size0, r) || cpar[r] != r) return;
+  if (r >= n_seg || cpar[r] != r) return;  // cluster roots only (a large segment's is -1)
   if (ccnt[r] > kBig) {
     big[atomicAdd(n_big, 1)] = r;
     return;
@@ -654,27 +783,28 @@ __global__ __launch_bounds__(kT) void k_root_flags(int n_seg, const int* mpar, i
   if (s < n_seg) flag[s] = mpar[s] == s;
 }
 
-// output per pixel: the id of its final segment (compact = 0), or the rank of
-// that segment among the image's final segments in id order (compact = 1;
-// rank = final roots before it in the batch minus those before the image's
-// first segment)
-__global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* segid, int* mpar,
-                                              const int* seg_root, const int* rank, int compact,
-                                              int32_t* out) {
+// output value of each segment: the id of its final segment (compact = 0),
+// or the rank of that segment among the image's final segments in id order
+// (compact = 1; rank = final roots before it in the batch minus those before
+// the image's first segment)
+__global__ __launch_bounds__(kT) void k_seg_out(const ImgDesc* img, int n_seg, const int* seg_img,
+                                                const int* segid, const int* mpar,
+                                                const int* seg_root, const int* rank, int compact,
+                                                int* val) {
+  const int s = blockIdx.x * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const int t = m_find(mpar, s);
+  const int64_t off = img[seg_img[s]].pix_off;
+  val[s] = compact ? rank[t] - rank[segid[off]] : (int)(seg_root[t] - off);
+}
+
+__global__ __launch_bounds__(kT) void k_final(const ImgDesc* img, const int* segid,
+                                              const int* val, int32_t* out) {
   int b, j, W, H;
   int64_t off;
   if (!img_pixel(img, b, j, W, H, off)) return;
   const int i = (int)(off + j);
-  int t = segid[i];
-  // walk to the final segment, halving the path (every write is an ancestor)
-  int u = mpar[t];
-  while (u != t) {
-    const int w = mpar[u];
-    mpar[t] = w;
-    t = u;
-    u = w;
-  }
-  out[i] = compact ? (int32_t)(rank[t] - rank[segid[off]]) : (int32_t)(seg_root[t] - off);
+  out[i] = val[segid[i]];
 }
 
 // per-image counts of small and merged segments: each block sums its
@@ -719,50 +849,56 @@ hipError_t scan(int* a, int n, int* bsum, int* total, hipStream_t s) {
 size_t conn_scan_blocks(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock); }
 
 size_t conn_tiles(int W, int H) {
-  return (size_t)((W + kTile - 1) / kTile) * (size_t)((H + kTile - 1) / kTile);
+  return (size_t)((W + kTW - 1) / kTW) * (size_t)((H + kTH - 1) / kTH);
 }
+
+size_t conn_side_ints(int n_img, int max_tiles) { return (size_t)n_img * max_tiles * kSide; }
 
 hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
                                   int max_pixels, int max_tiles, const int32_t* labels,
                                   hipStream_t s) {
-  const dim3 g(blocks(max_pixels), n_img);
-  hipLaunchKernelGGL(k_cc_tile, dim3(max_tiles, n_img), dim3(kT), 0, s, img, labels, C.par);
-  hipLaunchKernelGGL(k_cc_border, dim3(max_tiles, n_img), dim3(64), 0, s, img, labels, C.par);
-  hipLaunchKernelGGL(k_cc_flatten, g, dim3(kT), 0, s, img, C.par, C.scan);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return scan(C.scan, (int)C.n_pix, C.bsum, C.total, s);
+  (void)max_pixels;
+  hipLaunchKernelGGL(k_cc_tile, dim3(max_tiles, n_img), dim3(kT), 0, s, img, labels, C.par,
+                     C.side, max_tiles);
+  hipLaunchKernelGGL(k_cc_border, dim3(max_tiles, n_img), dim3(128), 0, s, img, labels, C.par,
+                     C.side, max_tiles);
+  // roots in raster order: ranks within blocks, then the scan of the block counts
+  const int n = (int)C.n_pix;
+  const int nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_root_rank, dim3(nb), dim3(kT), 0, s, C.par, n, C.scan, C.bsum);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kT), 0, s, C.bsum, nb, C.total);
+  return hipGetLastError();
 }
 
 hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
-                             int n_seg, const float* lab, int compact, int32_t* out,
-                             hipStream_t s) {
+                             int max_w, int max_h, int n_seg, const float* lab, int compact,
+                             int32_t* out, hipStream_t s) {
   const dim3 g(blocks(max_pixels), n_img);
+  const unsigned max_stat_tiles = (unsigned)(((max_w + kSW - 1) / kSW) * ((max_h + kSH - 1) / kSH));
   const unsigned gs = blocks(n_seg);
-  hipLaunchKernelGGL(k_seg_assign, g, dim3(kT), 0, s, img, C.par, C.scan, C.segid, C.seg_root,
-                     C.seg_img);
   hipLaunchKernelGGL(k_seg_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.size0, C.colsum, C.ccnt);
-  hipLaunchKernelGGL(k_seg_stats, g, dim3(kT), 0, s, img, lab, C.segid, C.size0, C.colsum);
-  hipLaunchKernelGGL(k_seg_prep, dim3(gs), dim3(kT), 0, s, n_seg, C.size0, C.colsum, C.size,
-                     C.mpar, C.cpar, C.next, C.tail);
-  hipLaunchKernelGGL(k_cl_link, g, dim3(kT), 0, s, img, C.segid, C.seg_img, C.size0, C.cpar);
-  hipLaunchKernelGGL(k_cl_count, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0,
-                     C.cpar, C.ccnt);
+  // (bsum still holds the block offsets of the root ranks here)
+  hipLaunchKernelGGL(k_seg_assign, dim3(max_stat_tiles, n_img), dim3(kT), 0, s, img, lab, C.par,
+                     C.scan, C.bsum, C.segid, C.seg_root, C.seg_img, C.size0, C.colsum);
+  hipLaunchKernelGGL(k_seg_prep, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0,
+                     C.colsum, C.size, C.mpar, C.cpar, C.next, C.tail);
+  hipLaunchKernelGGL(k_cl_link, g, dim3(kT), 0, s, img, C.segid, C.cpar);
+  hipLaunchKernelGGL(k_cl_count, dim3(gs), dim3(kT), 0, s, n_seg, C.cpar, C.ccnt);
   hipError_t e = hipMemcpyAsync(C.coff, C.ccnt, sizeof(int) * (size_t)n_seg,
                                 hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
   e = scan(C.coff, n_seg, C.bsum, C.total, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.cursor);
-  hipLaunchKernelGGL(k_cl_fill, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.cpar,
-                     C.coff, C.cursor, C.list, C.poff);
+  hipLaunchKernelGGL(k_cl_fill, dim3(gs), dim3(kT), 0, s, n_seg, C.size0, C.cpar, C.coff,
+                     C.cursor, C.list, C.poff);
   e = scan(C.poff, n_seg, C.bsum, C.total, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero, dim3(gs), dim3(kT), 0, s, n_seg, C.cursor);
   // the pixel union-find array is free now: it holds the sources' pixel lists
-  hipLaunchKernelGGL(k_px_fill, g, dim3(kT), 0, s, img, C.segid, C.seg_img, C.size0, C.poff,
-                     C.cursor, C.par);
-  // the pixel-flag scan array is free until the final ranks: it lists the large clusters
+  hipLaunchKernelGGL(k_px_fill, g, dim3(kT), 0, s, img, C.segid, C.cpar, C.poff, C.cursor,
+                     C.par);
+  // the root-rank array is free until the final ranks: it lists the large clusters
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(kT), 0, s, 1, C.n_big);
   hipLaunchKernelGGL(k_merge, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.cpar,
                      C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
@@ -772,12 +908,14 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
                      C.size0, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
                      reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail,
                      C.scan, C.n_big);
-  // the pixel-flag scan is free now: it ranks the final segments
+  // final segments ranked in id order; each segment's output value (into the
+  // working sizes, no longer needed); the output
   hipLaunchKernelGGL(k_root_flags, dim3(gs), dim3(kT), 0, s, n_seg, C.mpar, C.scan);
   e = scan(C.scan, n_seg, C.bsum, C.total, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final, g, dim3(kT), 0, s, img, C.segid, C.mpar, C.seg_root, C.scan, compact,
-                     out);
+  hipLaunchKernelGGL(k_seg_out, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.segid, C.mpar,
+                     C.seg_root, C.scan, compact, C.size);
+  hipLaunchKernelGGL(k_final, g, dim3(kT), 0, s, img, C.segid, C.size, out);
   hipLaunchKernelGGL(k_zero, dim3(blocks(4 * n_img)), dim3(kT), 0, s, 4 * n_img, C.counts);
   hipLaunchKernelGGL(k_counts, dim3(gs), dim3(kT), 0, s, img, n_seg, C.seg_img, C.size0, C.mpar,
                      C.counts);

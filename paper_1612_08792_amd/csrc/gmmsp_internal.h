@@ -141,19 +141,21 @@ struct ConnPtrs {
   int* bsum;                // scan block totals
   int* total;               // scan total (the number of segments after the first scan)
   int* n_big;               // number of clusters handled one wave each
+  int* side;                // per tile: labels and roots of its first and last columns
   int* counts;              // [n_img][4]: segments, small, merged, (unused)
   int *seg_root, *seg_img, *size0, *size, *ccnt, *coff, *cursor, *list, *poff;
   int *cpar, *mpar, *next, *tail;
   unsigned long long* colsum;  // [n_seg][3] quantised colour sums, then FP64 means
 };
 size_t conn_scan_blocks(int64_t n);
-size_t conn_tiles(int W, int H);  // 32 x 32 tiles of the component labelling
+size_t conn_tiles(int W, int H);  // 64 x 64 tiles of the component labelling
+size_t conn_side_ints(int n_img, int max_tiles);  // side buffer of the tile borders
 hipError_t conn_launch_components(const ConnPtrs& C, const ImgDesc* img, int n_img,
                                   int max_pixels, int max_tiles, const int32_t* labels,
                                   hipStream_t s);
 hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, int max_pixels,
-                             int n_seg, const float* lab, int compact, int32_t* out,
-                             hipStream_t s);
+                             int max_w, int max_h, int n_seg, const float* lab, int compact,
+                             int32_t* out, hipStream_t s);
 
 // Colour front end (gmmsp_color.hip).
 hipError_t launch_srgb8_to_lab(const uint8_t* rgb, int64_t n, float* lab, hipStream_t s);

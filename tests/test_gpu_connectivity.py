@@ -91,6 +91,33 @@ def test_checkerboard_is_one_cluster(dev):
     assert counts[0][0] == H * W
 
 
+def serpentine(H, W, period=4):
+    """A one-pixel path snaking over the whole image in a field of 0: rows
+    y = 0 mod period are full, joined at alternating ends, so the path crosses
+    every tile border many times and its union-find chains are long."""
+    labels = np.zeros((H, W), np.int64)
+    for y in range(0, H, period):
+        labels[y, :] = 1
+        if y + period < H:
+            x = W - 1 if (y // period) % 2 == 0 else 0
+            labels[y:y + period, x] = 1
+    return labels
+
+
+def test_long_components_across_tiles(dev):
+    rng = np.random.default_rng(17)
+    items = []
+    for H, W in [(150, 200), (129, 65)]:
+        items.append((serpentine(H, W), rng.uniform(0, 100, (H, W, 3)).astype(np.float32)))
+    # one-pixel vertical stripes (each a segment crossing every tile row) and a staircase
+    H, W = 140, 131
+    items.append(((np.arange(W)[None, :] % 2).repeat(H, 0), rng.uniform(0, 100, (H, W, 3)).astype(np.float32)))
+    H, W = 100, 100
+    stair = ((np.arange(H)[:, None] + np.arange(W)[None, :]) // 3) % 2
+    items.append((stair, rng.uniform(0, 100, (H, W, 3)).astype(np.float32)))
+    check_exact(dev, items, 8)
+
+
 def test_hand_cases(dev):
     # inherited neighbours: A joins B, B then joins Y through A's pixel
     labels = np.zeros((10, 10), np.int64)
