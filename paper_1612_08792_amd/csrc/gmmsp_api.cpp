@@ -1036,9 +1036,9 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
 namespace {
 
 struct MetricSizes {
-  size_t nlab, ngt, roff, toff, tab, sb, brp, rows, sums, total;
+  size_t nlab, ngt, roff, toff, tab, brp, rows, sums, total;
   int64_t tab_n, n_rows;
-  int max_pix;
+  int max_blocks;
   std::vector<int32_t> lab;       // label count per image
   std::vector<int64_t> row_off;   // n_img + 1
   std::vector<int64_t> tab_off;
@@ -1047,7 +1047,7 @@ struct MetricSizes {
 int metric_sizes(const gmmsp_handle* h, const int32_t* n_sp, const int32_t* n_gt, MetricSizes* z) {
   z->tab_n = 0;
   z->n_rows = 0;
-  z->max_pix = 0;
+  int max_w = 0, max_h = 0;
   z->lab.assign(h->n_img, 0);
   z->row_off.assign(h->n_img + 1, 0);
   z->tab_off.assign(h->n_img, 0);
@@ -1060,20 +1060,21 @@ int metric_sizes(const gmmsp_handle* h, const int32_t* n_sp, const int32_t* n_gt
     z->tab_off[b] = z->tab_n;
     z->tab_n += k * n_gt[b];
     z->row_off[b + 1] = z->row_off[b] + k;
-    z->max_pix = std::max(z->max_pix, h->img[b].W * h->img[b].H);
+    max_w = std::max(max_w, h->img[b].W);
+    max_h = std::max(max_h, h->img[b].H);
   }
   z->n_rows = z->row_off[h->n_img];
+  z->max_blocks = metrics_max_blocks(max_w, max_h);
   const size_t n_img = (size_t)h->n_img;
   z->nlab = align256(sizeof(int32_t) * n_img);
   z->ngt = align256(sizeof(int32_t) * n_img);
   z->roff = align256(sizeof(int64_t) * (n_img + 1));
   z->toff = align256(sizeof(int64_t) * n_img);
   z->tab = align256(sizeof(int) * (size_t)z->tab_n);
-  z->sb = align256((size_t)h->n_pix);
-  z->brp = align256(sizeof(int) * 2 * n_img * (size_t)metrics_max_blocks(z->max_pix));
+  z->brp = align256(sizeof(int) * 2 * n_img * (size_t)z->max_blocks);
   z->rows = align256(sizeof(int64_t) * (size_t)z->n_rows);
   z->sums = align256(sizeof(int64_t) * 4 * n_img + sizeof(int));
-  z->total = z->nlab + z->ngt + z->roff + z->toff + z->tab + z->sb + z->brp + 2 * z->rows + z->sums;
+  z->total = z->nlab + z->ngt + z->roff + z->toff + z->tab + z->brp + 2 * z->rows + z->sums;
   return GMMSP_OK;
 }
 
@@ -1107,7 +1108,6 @@ int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_
   int64_t* d_roff = (int64_t*)take(z.roff);
   int64_t* d_toff = (int64_t*)take(z.toff);
   int* d_tab = (int*)take(z.tab);
-  uint8_t* d_sb = (uint8_t*)take(z.sb);
   int* d_brp = (int*)take(z.brp);
   int64_t* d_rue = (int64_t*)take(z.rows);
   int64_t* d_rasa = (int64_t*)take(z.rows);
@@ -1122,8 +1122,8 @@ int gmmsp_metrics(gmmsp_handle* h, const int32_t* labels_dev, const int32_t* gt_
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_toff, z.tab_off.data(), sizeof(int64_t) * ni, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = metrics_launch(h->P, z.max_pix, labels_dev, gt_dev, d_nlab, d_ngt, d_roff, z.n_rows, d_toff,
-                       z.tab_n, d_tab, d_sb, d_brp, d_rue, d_rasa, d_sums, d_err, s);
+    e = metrics_launch(h->P, z.max_blocks, labels_dev, gt_dev, d_nlab, d_ngt, d_roff, z.n_rows,
+                       d_toff, z.tab_n, d_tab, d_brp, d_rue, d_rasa, d_sums, d_err, s);
   std::vector<int64_t> sums(4 * ni);
   int err = 0;
   if (e == hipSuccess)

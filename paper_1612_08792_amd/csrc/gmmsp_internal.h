@@ -161,11 +161,11 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
 hipError_t launch_srgb8_to_lab(const uint8_t* rgb, int64_t n, float* lab, hipStream_t s);
 
 // Accuracy measures (gmmsp_metrics.hip).
-int metrics_max_blocks(int max_pixels);
-hipError_t metrics_launch(const DevPtrs& P, int max_pixels, const int32_t* sp, const int32_t* gt,
+int metrics_max_blocks(int max_w, int max_h);  // pixel-pass tiles of the largest image
+hipError_t metrics_launch(const DevPtrs& P, int max_blocks, const int32_t* sp, const int32_t* gt,
                           const int32_t* n_lab, const int32_t* n_gt, const int64_t* row_off,
                           int64_t n_rows, const int64_t* tab_off, int64_t tab_n, int* tab,
-                          uint8_t* sb, int* br_part, int64_t* row_ue, int64_t* row_asa,
-                          int64_t* sums, int* err, hipStream_t s);
+                          int* br_part, int64_t* row_ue, int64_t* row_asa, int64_t* sums,
+                          int* err, hipStream_t s);
 
 }  // namespace gmmsp

@@ -88,6 +88,22 @@ def test_synthetic_pairs_uneven_batch(dev):
         check(vals, sums, M.metrics(sp_maps[b], gt_maps[b]), b)
 
 
+def test_many_region_ids_and_fragmented_labels(dev):
+    # region ids spread over [0, 6000): table rows longer than the part the row
+    # pass keeps in registers; a noisy superpixel map with many runs per row
+    W, H = 150, 70
+    rng = np.random.default_rng(7)
+    gt = synth.voronoi_lab(W, H, 40, 3.0, 300, 30).regions.numpy()
+    ids = rng.permutation(6000)[:40]
+    gt = ids[gt]
+    sp = synth.voronoi_lab(W, H, 25, 3.0, 301, 30).regions.numpy()
+    flip = rng.random((H, W)) < 0.2
+    sp = np.where(flip, rng.integers(0, 25, (H, W)), sp)
+    (vals, sums), m = gpu_metrics(dev, [(W, H)], [40], [sp], [gt], [6000])
+    assert m.grids[0].K >= 25
+    check(vals, sums, M.metrics(sp, gt), 0)
+
+
 def test_out_of_range_values_are_an_error(dev):
     W, H = 30, 20
     sp = np.zeros((H, W), np.int64)
