@@ -168,11 +168,21 @@ __global__ __launch_bounds__(kT) void k_cc_tile(const ImgDesc* img, const int32_
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = x0 + lane;
   const bool xin = x < W;
-  // labels and run heads (pixels outside the image are runs of their own)
-  for (int ty = wv; ty < kTH; ty += kTileWaves) {
+  // labels and run heads (pixels outside the image are runs of their own);
+  // the wave's rows are loaded first, so their loads are in flight together
+  constexpr int kRows = kTH / kTileWaves;
+  int32_t labs[kRows];
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    const int ty = wv + q * kTileWaves;
+    labs[q] = xin && y0 + ty < H ? labels[off + (int64_t)(y0 + ty) * W + x] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    const int ty = wv + q * kTileWaves;
     const bool in = xin && y0 + ty < H;
     const int l = ty * kTW + lane;
-    const int32_t lab = in ? labels[off + (int64_t)(y0 + ty) * W + x] : 0;
+    const int32_t lab = labs[q];
     ll[l] = lab;
     const int32_t left = __shfl_up(lab, 1, 64);
     const unsigned long long heads = __ballot(lane == 0 || left != lab || !in);
@@ -292,16 +302,6 @@ __global__ __launch_bounds__(kT) void k_root_rank(const int* par, int n, int* ra
     run += v[k];
   }
   if (threadIdx.x == kT - 1) bsum[blockIdx.x] = sh[kT - 1];
-}
-
-// the root of pixel i (no joins run any more, so plain loads)
-__device__ __forceinline__ int px_root(const int* par, int i) {
-  int x = par[i], y = par[x];
-  while (y != x) {
-    x = y;
-    y = par[x];
-  }
-  return x;
 }
 
 // ---- exclusive scan of int32 (in place), total to *total ---------------------
@@ -450,22 +450,47 @@ __global__ __launch_bounds__(kT) void k_seg_assign(const ImgDesc* img, const flo
   const int x0 = (blockIdx.x % tiles_x) * kSW, y0 = (blockIdx.x / tiles_x) * kSH;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool xin = x0 + lane < W;
-  for (int ty = wv; ty < kSH; ty += kTileWaves) {
+  // the wave's rows: loads first (colours, parents), then the roots and the
+  // segment indices, each step's loads in flight together
+  constexpr int kRows = kSH / kTileWaves;
+  int pi[kRows], pr[kRows], ps[kRows];
+  float pc[kRows][3];
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int ty = wv + u * kTileWaves;
     const bool in = xin && y0 + ty < H;
-    int s = -1, cnt = 0;
+    pi[u] = in ? (int)(I.pix_off + (int64_t)(y0 + ty) * W + x0 + lane) : -1;
+    pr[u] = in ? par[pi[u]] : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pc[u][c] = in ? lab[3 * (int64_t)pi[u] + c] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    if (pi[u] < 0) continue;
+    int y = par[pr[u]];
+    while (y != pr[u]) {
+      pr[u] = y;
+      y = par[y];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) ps[u] = pi[u] >= 0 ? rank[pr[u]] + boff[pr[u] / kScanBlock] : -1;
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const bool in = pi[u] >= 0;
+    const int s = ps[u];
+    int cnt = 0;
     long long q[3] = {0, 0, 0};
     if (in) {
-      const int i = (int)(I.pix_off + (int64_t)(y0 + ty) * W + x0 + lane);
-      const int r = px_root(par, i);
-      s = rank[r] + boff[r / kScanBlock];
+      const int i = pi[u];
       segid[i] = s;
-      if (r == i) {
+      if (pr[u] == i) {
         seg_root[s] = i;
         seg_img[s] = b;
       }
       cnt = 1;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) q[c] = (long long)rint((double)lab[3 * (int64_t)i + c] * 1048576.0);
+      for (int c = 0; c < 3; ++c) q[c] = (long long)rint((double)pc[u][c] * 1048576.0);
     }
     // runs of equal segment: the head lane of each, then sums within runs
     const int sl = __shfl_up(s, 1, 64);

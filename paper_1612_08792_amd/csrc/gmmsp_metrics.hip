@@ -84,20 +84,33 @@ __global__ __launch_bounds__(kT) void k_m_pix(const ImgDesc* img, const int32_t*
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = x0 + lane;
   int nhit = 0, ngb = 0;
-  for (int ty = wv; ty < kMH; ty += kT / 64) {
+  // the wave's rows of region ids (and their right and lower neighbours) first
+  constexpr int kRows = kMH / (kT / 64);
+  int gq[kRows][3];
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int y = y0 + wv + u * (kT / 64);
+    const int64_t i = off + (int64_t)y * W + x;
+    const bool in = x < W && y < H;
+    gq[u][0] = in ? gt[i] : 0;
+    gq[u][1] = in && x + 1 < W ? gt[i + 1] : gq[u][0];
+    gq[u][2] = in && y + 1 < H ? gt[i + W] : gq[u][0];
+  }
+#pragma unroll
+  for (int u = 0; u < kRows; ++u) {
+    const int ty = wv + u * (kT / 64);
     const int y = y0 + ty;
     const bool in = x < W && y < H;
     int key = -1;
     bool gb = false, hit = false;
     if (in) {
-      const int64_t i = off + (int64_t)y * W + x;
-      const int k = hs[(ty + kR) * kHW + lane + kR], g = gt[i];
+      const int k = hs[(ty + kR) * kHW + lane + kR], g = gq[u][0];
       if (k < 0 || k >= K || g < 0 || g >= G) {
         atomicOr(err, 1);
       } else {
         key = k * G + g;
       }
-      gb = (x + 1 < W && gt[i + 1] != g) || (y + 1 < H && gt[i + W] != g);
+      gb = gq[u][1] != g || gq[u][2] != g;
       if (gb) {  // a superpixel boundary pixel in the 5 x 5 square (the halo is 0 outside)
         const uint8_t* c = hb + ty * kBW + lane;
 #pragma unroll
