@@ -26,12 +26,14 @@
 // parallel.  Merges into a large segment from several clusters only add to
 // its size, which no decision reads (a large segment is never merged).
 //
-// Steps: pixel union-find of equal-label 4-neighbours (roots are the minimum
-// index, so the partition and ids are unique whatever the order of the
-// atomics); compaction of the roots to segment indices (in id order); sizes
-// and integer colour sums with integer atomics (exact); cluster union-find
-// over adjacent small segments; per-cluster lists sorted by (size, id) with
-// a heap sort; per-source pixel lists; the sequential merge per cluster; the
+// Steps: pixel union-find of equal-label 4-neighbours, in 64 x 64 tiles in
+// LDS and then across tile borders (roots are the minimum index, so the
+// partition and ids are unique whatever the order of the atomics); ranks of
+// the roots in raster order (segment indices, in id order); sizes and integer
+// colour sums, gathered per block in LDS and added with integer atomics
+// (exact); cluster union-find over adjacent small segments; per-cluster lists
+// sorted by (size, id); per-source pixel lists; the sequential merge per
+// cluster (one thread for small clusters, one wave for large ones); the
 // output ids.
 #include "gmmsp_internal.h"
 
