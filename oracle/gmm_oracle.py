@@ -17,10 +17,17 @@ Conventions and readings (the paper is silent or garbled on these):
   column / row of windows reach the image border (no re-centring of seeds);
 * cov_mode 0 (default): block-diagonal Sigma = diag(Sigma_s (x,y), sigma_L^2,
   Sigma_(a,b)) per Eq. BlockSigma1; cov_mode 1: diag(Sigma_s, Sigma_(L,a,b)) per
-  Eq. BlockSigma;
+  Eq. BlockSigma; cov_mode 2: the full 5 x 5 Sigma of Eq. UpdateSig; cov_mode 3:
+  a grayscale image, z_i = (x_i, y_i, I_i) with D = 3 and Sigma = diag(Sigma_s,
+  sigma_I^2) (Sec. III-A, III-C);
 * shape control clamps each eigenvalue of each block from below:
   lambda~ = max(lambda, eps), eps_s = 2 for the spatial block, eps_c for every
-  colour block (Eqs. mlams, mlamc; the first branch keeps lambda(j) itself);
+  colour (or intensity) block (Eqs. mlams, mlamc; the first branch keeps
+  lambda(j) itself).  The paper defines the floors per block only; for the full
+  Sigma (cov_mode 2) the floors act on Sigma scaled by F = diag(eps_s, eps_s,
+  eps_c, eps_c, eps_c): the eigenvalues of F^-1/2 Sigma F^-1/2 are raised to 1,
+  which is the paper's rule whenever Sigma is block diagonal and the maximum of
+  the Gaussian likelihood under Sigma >= F in general;
 * init (Sec. III-C): mu_k = z_j at the seed pixel
   j = k_x v_x + v_x // 2 + W (k_y v_y + v_y // 2), Sigma_s = diag(v_x^2, v_y^2),
   every colour variance lambda^2 (lambda = 8), colour covariances 0;
@@ -45,7 +52,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 LN_2PI = math.log(2.0 * math.pi)
-D = 5                                   # components of z = (x, y, L, a, b)
+D = 5                                   # components of z = (x, y, L, a, b) of a colour image
 MAXC = 9                                # |K_i| <= 9 (Sec. III-D)
 
 
@@ -131,10 +138,13 @@ def window_positions(g: Grid, cand: np.ndarray):
 
 
 def features(lab) -> np.ndarray:
-    """z_i = (x_i, y_i, L_i, a_i, b_i) in float64, shape (H, W, 5)."""
+    """z_i = (x_i, y_i, c_i) in float64: (H, W, 5) for a CIELAB image (H, W, 3),
+    (H, W, 3) for a grayscale image (H, W) or (H, W, 1)."""
     lab = np.asarray(lab, dtype=np.float32)
-    H, W, _ = lab.shape
-    z = np.empty((H, W, D), dtype=np.float64)
+    if lab.ndim == 2:
+        lab = lab[..., None]
+    H, W, C = lab.shape
+    z = np.empty((H, W, 2 + C), dtype=np.float64)
     z[..., 0] = np.arange(W, dtype=np.float64)[None, :]
     z[..., 1] = np.arange(H, dtype=np.float64)[:, None]
     z[..., 2:] = lab.astype(np.float64)
@@ -150,7 +160,7 @@ class Params:
     eps_s: float = 2.0          # spatial eigenvalue floor (Sec. III-C)
     eps_c: float = 8.0          # colour eigenvalue floor (Sec. IV-A)
     lam: float = 8.0            # initial colour std (Sec. III-C, Sec. IV-A)
-    cov_mode: int = 0           # 0: {xy, L, ab}; 1: {xy, Lab}
+    cov_mode: int = 0           # 0: {xy, L, ab}; 1: {xy, Lab}; 2: full 5x5; 3: grayscale {xy, I}
     n_min: float = 1e-3         # mass guard
 
 
@@ -160,17 +170,27 @@ def blocks(cov_mode: int):
         return [(0, 1), (2,), (3, 4)]           # Eq. BlockSigma1
     if cov_mode == 1:
         return [(0, 1), (2, 3, 4)]              # Eq. BlockSigma
-    raise ValueError("cov_mode must be 0 or 1")
+    if cov_mode == 2:
+        return [(0, 1, 2, 3, 4)]                # Eq. UpdateSig, full
+    if cov_mode == 3:
+        return [(0, 1), (2,)]                   # grayscale, D = 3
+    raise ValueError("cov_mode must be 0, 1, 2 or 3")
 
 
 def block_eps(cov_mode: int, p: Params):
     return [p.eps_s] + [p.eps_c] * (len(blocks(cov_mode)) - 1)
 
 
+def component_floors(cov_mode: int, p: Params) -> np.ndarray:
+    """The floor of each component's scale: eps_s for x, y, eps_c for colour."""
+    n = 3 if cov_mode == 3 else D
+    return np.array([p.eps_s, p.eps_s] + [p.eps_c] * (n - 2))
+
+
 @dataclass
 class Theta:
-    mu: np.ndarray              # (K, 5)
-    sigma: np.ndarray           # (K, 5, 5) block diagonal
+    mu: np.ndarray              # (K, Dz), Dz = 5 (colour) or 3 (grayscale)
+    sigma: np.ndarray           # (K, Dz, Dz), block diagonal or full
     mass: np.ndarray = field(default=None)   # (K,) N_k of the M-step that made it
 
     def copy(self) -> "Theta":
@@ -185,13 +205,14 @@ def seed_index(g: Grid, k):
 
 
 def init_theta(g: Grid, z: np.ndarray, p: Params) -> Theta:
-    zf = z.reshape(-1, D)
+    dz = z.shape[-1]
+    zf = z.reshape(-1, dz)
     ks = np.arange(g.K)
     mu = zf[seed_index(g, ks)].copy()
-    sigma = np.zeros((g.K, D, D))
+    sigma = np.zeros((g.K, dz, dz))
     sigma[:, 0, 0] = g.vx ** 2
     sigma[:, 1, 1] = g.vy ** 2
-    for c in (2, 3, 4):
+    for c in range(2, dz):
         sigma[:, c, c] = p.lam ** 2
     return Theta(mu, sigma, np.zeros(g.K))
 
@@ -214,13 +235,13 @@ def _block_inverses(theta: Theta, cov_mode: int):
 
 def log_density_pairs(zs: np.ndarray, ks: np.ndarray, theta: Theta,
                       cov_mode: int = 0, inv=None) -> np.ndarray:
-    """ln p(z; theta_k) (Eq. gaussian, D = 5) for rows zs (n, 5) and
+    """ln p(z; theta_k) (Eq. gaussian, D = zs.shape[1]) for rows zs (n, D) and
     superpixels ks (n,).  With Sigma block diagonal, ln det Sigma is the sum
     over blocks and the quadratic form splits into one form per block."""
     if inv is None:
         inv = _block_inverses(theta, cov_mode)
     d = zs - theta.mu[ks]
-    out = np.full(zs.shape[0], -0.5 * D * LN_2PI)
+    out = np.full(zs.shape[0], -0.5 * zs.shape[1] * LN_2PI)
     for idx, P, logdet in inv:
         db = d[:, idx]
         q = np.einsum("ni,nij,nj->n", db, P[ks], db)
@@ -235,7 +256,7 @@ def estep(z: np.ndarray, cand: np.ndarray, theta: Theta, cov_mode: int = 0):
     Returns (R, logp, L) with R and logp shaped like ``cand`` (missing
     candidates: R = 0, logp = -inf)."""
     shp = cand.shape
-    zf = z.reshape(-1, D)
+    zf = z.reshape(-1, z.shape[-1])
     cf = cand.reshape(-1, MAXC)
     inv = _block_inverses(theta, cov_mode)
     logp = np.full(cf.shape, -np.inf)
@@ -265,6 +286,16 @@ def clamp_eigen(S: np.ndarray, eps: float) -> np.ndarray:
     return (Q * w[None, :]) @ Q.T
 
 
+def clamp_eigen_scaled(S: np.ndarray, floors) -> np.ndarray:
+    """Shape control of a full Sigma: with F = diag(floors), the eigenvalues of
+    F^-1/2 S F^-1/2 are raised to at least 1 and the result scaled back."""
+    f = np.sqrt(np.asarray(floors, dtype=np.float64))
+    T = S / np.outer(f, f)
+    w, Q = np.linalg.eigh(T)
+    w = np.where(w >= 1.0, w, 1.0)
+    return np.outer(f, f) * ((Q * w[None, :]) @ Q.T)
+
+
 def mstep_one(zw: np.ndarray, rk: np.ndarray, mu_old: np.ndarray,
               sigma_old: np.ndarray, p: Params):
     """M-step for one superpixel from the pixels of its window I_k (rows zw)
@@ -273,11 +304,15 @@ def mstep_one(zw: np.ndarray, rk: np.ndarray, mu_old: np.ndarray,
     if not Nk >= p.n_min:
         return mu_old.copy(), sigma_old.copy(), Nk
     mu = (rk[:, None] * zw).sum(axis=0) / Nk                    # Eq. UpdateMu
-    sigma = np.zeros((D, D))
+    dz = zw.shape[1]
+    sigma = np.zeros((dz, dz))
     for idx, eps in zip(blocks(p.cov_mode), block_eps(p.cov_mode, p)):
         db = zw[:, idx] - mu[list(idx)]
         Sb = (rk[:, None, None] * db[:, :, None] * db[:, None, :]).sum(axis=0) / Nk
-        Sb = clamp_eigen(Sb, eps)
+        if p.cov_mode == 2:
+            Sb = clamp_eigen_scaled(Sb, component_floors(2, p))
+        else:
+            Sb = clamp_eigen(Sb, eps)
         sigma[np.ix_(idx, idx)] = Sb
     return mu, sigma, Nk
 
@@ -287,7 +322,7 @@ def mstep(z: np.ndarray, g: Grid, R: np.ndarray, pos, theta: Theta, p: Params) -
     new = Theta(np.empty_like(theta.mu), np.empty_like(theta.sigma), np.empty(g.K))
     for k in range(g.K):
         xb, xe, yb, ye = window(g, k)
-        zw = z[yb:ye, xb:xe].reshape(-1, D)
+        zw = z[yb:ye, xb:xe].reshape(-1, z.shape[-1])
         rk = np.take_along_axis(R[yb:ye, xb:xe], pos[k][..., None], axis=-1).reshape(-1)
         new.mu[k], new.sigma[k], new.mass[k] = mstep_one(zw, rk, theta.mu[k],
                                                          theta.sigma[k], p)
@@ -394,6 +429,43 @@ def theta_to_rows(theta: Theta) -> np.ndarray:
     out[:, 11] = s[:, 4, 4]
     out[:, 12] = 0.0 if theta.mass is None else theta.mass
     return out
+
+
+# full Sigma (cov_mode 2): mu (5), the upper triangle of Sigma row by row
+# (xx xy xL xa xb yy yL ya yb LL La Lb aa ab bb), N_k: 21 values;
+# grayscale (cov_mode 3): mu_x mu_y mu_I S_xx S_xy S_yy S_II N_k: 8 values
+ROW_FULL = [(i, j) for i in range(D) for j in range(i, D)]
+ROW_GRAY = [(0, 0), (0, 1), (1, 1), (2, 2)]
+
+
+def theta_to_rows_mode(theta: Theta, cov_mode: int) -> np.ndarray:
+    """Export rows of any cov_mode (0 and 1 as theta_to_rows, theta_to_rows3)."""
+    if cov_mode == 0:
+        return theta_to_rows(theta)
+    if cov_mode == 1:
+        return theta_to_rows3(theta)
+    layout = ROW_FULL if cov_mode == 2 else ROW_GRAY
+    dz = theta.mu.shape[1]
+    out = np.zeros((theta.mu.shape[0], dz + len(layout) + 1))
+    out[:, :dz] = theta.mu
+    for c, (i, j) in enumerate(layout):
+        out[:, dz + c] = theta.sigma[:, i, j]
+    out[:, -1] = 0.0 if theta.mass is None else theta.mass
+    return out
+
+
+def rows_mode_to_theta(rows: np.ndarray, cov_mode: int) -> Theta:
+    if cov_mode == 0:
+        return rows_to_theta(rows)
+    if cov_mode == 1:
+        return rows3_to_theta(rows)
+    rows = np.asarray(rows, dtype=np.float64)
+    layout = ROW_FULL if cov_mode == 2 else ROW_GRAY
+    dz = D if cov_mode == 2 else 3
+    s = np.zeros((rows.shape[0], dz, dz))
+    for c, (i, j) in enumerate(layout):
+        s[:, i, j] = s[:, j, i] = rows[:, dz + c]
+    return Theta(rows[:, :dz].copy(), s, rows[:, -1].copy())
 
 
 def rows_to_theta(rows: np.ndarray) -> Theta:
