@@ -16,7 +16,10 @@
  * Conventions shared by every entry point
  *   - Image data: interleaved float32 CIELAB (L, a, b) per pixel, row-major,
  *     pixel index i = x + W y.  A batch is packed back to back: image b starts
- *     at pixel offset P_b = sum_{c<b} W_c H_c, i.e. at float 3 P_b.
+ *     at pixel offset P_b = sum_{c<b} W_c H_c, i.e. at float 3 P_b.  With
+ *     cov_mode 3 (grayscale) the EM entry points take one float32 intensity per
+ *     pixel instead (image b at float P_b); the connectivity step always takes
+ *     three channels (pass (I, 0, 0) for a grayscale image).
  *   - Superpixel k of an image is k = k_y n_x + k_x (Eq. kxy); batch-wide
  *     tables list the superpixels of image 0, then of image 1, and so on.
  *   - Device pointers (suffix _dev) are owned by the caller, who allocates
@@ -57,8 +60,15 @@ typedef struct gmmsp_params {
   double eps_c;         /* colour eigenvalue floor (paper: 8, Sec. IV-A)             */
   double lambda;        /* initial colour standard deviation (paper: 8, Sec. IV-A)   */
   int32_t cov_mode;     /* 0: blocks {(x,y), L, (a,b)} (Eq. BlockSigma1);            */
-                        /* 1: blocks {(x,y), (L,a,b)} (Eq. BlockSigma); one value    */
-                        /*    for every image of a batch                             */
+                        /* 1: blocks {(x,y), (L,a,b)} (Eq. BlockSigma);              */
+                        /* 2: the full 5x5 Sigma (Eq. UpdateSig), its eigenvalue     */
+                        /*    floors applied to Sigma scaled by diag(eps_s, eps_s,   */
+                        /*    eps_c, eps_c, eps_c) (the per-block rule of Eqs.       */
+                        /*    mlams, mlamc whenever Sigma is block diagonal);        */
+                        /* 3: a grayscale image, z = (x, y, I), D = 3 (Sec. III-A),  */
+                        /*    blocks {(x,y), I}; the image buffer holds one float    */
+                        /*    per pixel instead of three.                            */
+                        /* One value for every image of a batch.                     */
   double n_min;         /* a superpixel with mass sum_i R_ik < n_min keeps theta_k   */
 } gmmsp_params;
 
@@ -75,9 +85,15 @@ typedef struct gmmsp_handle gmmsp_handle;
  * (mean, the blocks of Sigma_k per Eq. BlockSigma1, and the mass
  * N_k = sum_{i in I_k} R_ik of the M-step that produced them); 15 doubles with
  * cov_mode 1 (the 3x3 colour block of Eq. BlockSigma):
- *   mu_x mu_y mu_L mu_a mu_b  S_xx S_xy S_yy  S_LL S_La S_Lb S_aa S_ab S_bb  N_k */
+ *   mu_x mu_y mu_L mu_a mu_b  S_xx S_xy S_yy  S_LL S_La S_Lb S_aa S_ab S_bb  N_k
+ * 21 doubles with cov_mode 2 (the upper triangle of the full Sigma row by row):
+ *   mu (5)  S_xx S_xy S_xL S_xa S_xb S_yy S_yL S_ya S_yb S_LL S_La S_Lb S_aa S_ab S_bb  N_k
+ * 8 doubles with cov_mode 3 (grayscale):
+ *   mu_x mu_y mu_I  S_xx S_xy S_yy  S_II  N_k */
 #define GMMSP_THETA_ROW 13
 #define GMMSP_THETA_ROW3 15
+#define GMMSP_THETA_ROW_FULL 21
+#define GMMSP_THETA_ROW_GRAY 8
 
 /* Largest number of E-steps whose log-likelihood one handle records per image
  * between two initialisations. */
@@ -90,7 +106,7 @@ int gmmsp_grid(const gmmsp_params* params, gmmsp_grid_info* out);
 
 /* Host only.  Device workspace, in bytes, for a batch of n_images images with
  * parameters params[0..n_images-1].  Errors: those of gmmsp_grid, E_INVAL for
- * cov_mode not 0 or 1, different cov_mode values in one batch, or a
+ * cov_mode outside 0..3, different cov_mode values in one batch, or a
  * non-positive eps_s, eps_c, lambda. */
 int gmmsp_workspace_bytes(int32_t n_images, const gmmsp_params* params, size_t* bytes);
 
@@ -115,8 +131,8 @@ int gmmsp_image_grid(const gmmsp_handle* h, int32_t b, gmmsp_grid_info* out);
  * image.  lab_dev: packed batch (see above). */
 int gmmsp_init_seeds(gmmsp_handle* h, const float* lab_dev, void* stream);
 
-/* Set theta for every superpixel from rows of GMMSP_THETA_ROW (cov_mode 1:
- * GMMSP_THETA_ROW3) doubles (device
+/* Set theta for every superpixel from rows of the cov_mode's width
+ * (GMMSP_THETA_ROW, _ROW3, _ROW_FULL, _ROW_GRAY) doubles (device
  * memory, batch order; N_k ignored), applying the shape-control eigenvalue floors
  * of Eqs. mlams and mlamc, and reset the iteration state.  This is the warm-start
  * entry point and the resume hook. */
@@ -125,8 +141,7 @@ int gmmsp_set_params_dev(gmmsp_handle* h, const double* theta_dev, void* stream)
 /* The same from host memory (copied on `stream`, which is synchronised). */
 int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream);
 
-/* Copy theta (rows of GMMSP_THETA_ROW, cov_mode 1: GMMSP_THETA_ROW3, doubles,
- * batch order) to the host. */
+/* Copy theta (rows of the cov_mode's width, doubles, batch order) to the host. */
 int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream);
 
 /* EM iterations (Algorithm 1, steps 2-6).  Each pass t evaluates the E-step
@@ -166,8 +181,8 @@ int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream);
 /* Schedule of the statistics pass: how many 64-lane waves share one v_x x v_y
  * cell (1, 2 or 4; default 1).  More waves per cell raise the parallelism of
  * small batches; every schedule gives the same result up to the grouping of the
- * FP64 sums (each schedule is itself bitwise repeatable).  With cov_mode 1 only
- * 1 is accepted (E_INVAL otherwise). */
+ * FP64 sums (each schedule is itself bitwise repeatable).  With cov_mode 1, 2
+ * or 3 only 1 is accepted (E_INVAL otherwise). */
 #define GMMSP_MAX_WAVES_PER_CELL 4
 int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell);
 int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
@@ -176,7 +191,7 @@ int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
  * grid initialisation for each schedule 1, 2, 4 with HIP events on `stream`,
  * keeps the fastest (ties to fewer waves), and leaves the handle initialised
  * by gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times (-1
- * for a schedule not timed; with cov_mode 1 only schedule 1 is). */
+ * for a schedule not timed; with cov_mode 1, 2 or 3 only schedule 1 is). */
 int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
                    int32_t* chosen, void* stream);
 
@@ -238,7 +253,7 @@ typedef enum gmmsp_ws_buffer {
 
 /* Device workspace of the warm start for this handle's batch, and attaching it
  * (builds the seed-grid neighbour table on `stream`, then synchronises it).
- * The network predicts the split colour blocks: E_INVAL with cov_mode 1. */
+ * The network predicts the split colour blocks: E_INVAL with cov_mode 1, 2, 3. */
 int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes);
 int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream);
 

@@ -18,6 +18,9 @@ GMMSP_E_HIP = -3
 GMMSP_E_STATE = -5
 THETA_ROW = 13
 THETA_ROW3 = 15
+THETA_ROW_FULL = 21
+THETA_ROW_GRAY = 8
+THETA_ROWS = {0: THETA_ROW, 1: THETA_ROW3, 2: THETA_ROW_FULL, 3: THETA_ROW_GRAY}
 LL_CAP = 4096
 
 

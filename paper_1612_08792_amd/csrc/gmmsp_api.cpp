@@ -67,8 +67,8 @@ int grid_of(const gmmsp_params* p, gmmsp_grid_info* g) {
 int check_params(const gmmsp_params* p) {
   if (!(p->eps_s > 0) || !(p->eps_c > 0) || !(p->lambda > 0) || !(p->n_min >= 0))
     return fail(GMMSP_E_INVAL, "eps_s, eps_c, lambda must be > 0 and n_min >= 0");
-  if (p->cov_mode != 0 && p->cov_mode != 1)
-    return fail(GMMSP_E_INVAL, "cov_mode %d is not supported (0 or 1)", p->cov_mode);
+  if (p->cov_mode < 0 || p->cov_mode > 3)
+    return fail(GMMSP_E_INVAL, "cov_mode %d is not supported (0, 1, 2 or 3)", p->cov_mode);
   return GMMSP_OK;
 }
 
@@ -78,7 +78,7 @@ struct Layout {
   size_t img, state, ll_hist, cell, sp, theta, rec, part, llp, n_done, total;
   int32_t n_cell = 0, n_sp = 0;
   int64_t n_pix = 0;
-  int32_t cov3 = 0;
+  int32_t cov_mode = 0;
 };
 
 int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>* descs) {
@@ -105,9 +105,12 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
       d.ncells = g.ncx * g.ncy;
       d.eps_s = params[b].eps_s; d.eps_c = params[b].eps_c;
       d.lam = params[b].lambda; d.n_min = params[b].n_min;
-      // ln of the largest density the eigenvalue floors allow:
-      // -(5/2) ln 2pi - (1/2)(2 ln eps_s + 3 ln eps_c)
-      d.lncmax = -2.5 * log(2.0 * M_PI) - 0.5 * (2.0 * log(d.eps_s) + 3.0 * log(d.eps_c));
+      // ln of the largest density the eigenvalue floors allow (det Sigma >= the
+      // product of the floors): -(D/2) ln 2pi - (1/2)(2 ln eps_s + (D - 2) ln eps_c),
+      // D = 5, or 3 for a grayscale image
+      const double dim = params[b].cov_mode == 3 ? 3.0 : 5.0;
+      d.lncmax = -0.5 * dim * log(2.0 * M_PI) -
+                 0.5 * (2.0 * log(d.eps_s) + (dim - 2.0) * log(d.eps_c));
     }
     n_cell += (int64_t)g.ncx * g.ncy;
     n_sp += g.K;
@@ -120,9 +123,9 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
   L->ll_hist = o; o = align256(o + sizeof(double) * (size_t)kLLCap * n);
   L->cell = o;    o = align256(o + sizeof(CellDesc) * n_cell);
   L->sp = o;      o = align256(o + sizeof(SpDesc) * n_sp);
-  L->cov3 = params[0].cov_mode == 1;
-  L->theta = o;   o = align256(o + sizeof(double) * (L->cov3 ? kThetaRow3 : kThetaRow) * n_sp);
-  L->rec = o;     o = align256(o + sizeof(float) * (L->cov3 ? kRec3 : kRecFloats) * kSlots * n_cell);
+  L->cov_mode = params[0].cov_mode;
+  L->theta = o;   o = align256(o + sizeof(double) * theta_row_of(L->cov_mode) * n_sp);
+  L->rec = o;     o = align256(o + sizeof(float) * rec_floats_of(L->cov_mode) * kSlots * n_cell);
   L->part = o;    o = align256(o + sizeof(double) * kPartStride * kMaxWpc * n_cell);
   L->llp = o;     o = align256(o + sizeof(double) * kMaxWpc * n_cell);
   L->n_done = o;  o = align256(o + sizeof(int32_t));
@@ -292,7 +295,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.n_cell = L.n_cell;
   P.n_sp = L.n_sp;
   P.wpc = 1;
-  P.cov3 = L.cov3;
+  P.cov_mode = L.cov_mode;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -363,7 +366,7 @@ int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
   if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
   // stage the rows in the partials area, which the next pass overwrites anyway
-  const size_t bytes = sizeof(double) * (h->P.cov3 ? kThetaRow3 : kThetaRow) * (size_t)h->P.n_sp;
+  const size_t bytes = sizeof(double) * theta_row_of(h->P.cov_mode) * (size_t)h->P.n_sp;
   if (bytes > sizeof(double) * kPartStride * (size_t)h->P.n_cell)
     return fail(GMMSP_E_SIZE, "staging area too small");
   hipError_t e = hipMemcpyAsync(h->P.part, theta_host, bytes, hipMemcpyHostToDevice, s);
@@ -378,7 +381,7 @@ int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
 int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
   if (!h || !theta_host) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
-  const size_t row = h->P.cov3 ? kThetaRow3 : kThetaRow;
+  const size_t row = theta_row_of(h->P.cov_mode);
   hipError_t e = hipMemcpyAsync(theta_host, h->P.theta, sizeof(double) * row * (size_t)h->P.n_sp,
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -597,8 +600,8 @@ int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (waves_per_cell != 1 && waves_per_cell != 2 && waves_per_cell != 4)
     return fail(GMMSP_E_INVAL, "waves per cell must be 1, 2 or 4");
-  if (h->P.cov3 && waves_per_cell != 1)
-    return fail(GMMSP_E_INVAL, "the 3x3 colour block (cov_mode 1) runs one wave per cell");
+  if (h->P.cov_mode != 0 && waves_per_cell != 1)
+    return fail(GMMSP_E_INVAL, "cov_mode %d runs one wave per cell", h->P.cov_mode);
   h->P.wpc = waves_per_cell;
   return GMMSP_OK;
 }
@@ -622,7 +625,7 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
   const int32_t cand[3] = {1, 2, 4};
-  const int n_cand = h->P.cov3 ? 1 : 3;  // the 3x3 colour block has one schedule
+  const int n_cand = h->P.cov_mode != 0 ? 1 : 3;  // the other covariance models have one schedule
   if (ms_host)
     for (int c = 0; c < 3; ++c) ms_host[c] = -1.0;
   double best = 0.0;
@@ -776,14 +779,14 @@ hipError_t ws_forward_range(gmmsp_handle* h, const float* params, int p0, int p1
 
 int gmmsp_ws_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
   if (!h || !bytes) return fail(GMMSP_E_INVAL, "null pointer");
-  if (h->P.cov3) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
+  if (h->P.cov_mode != 0) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
   *bytes = ws_sizes(h).total;
   return GMMSP_OK;
 }
 
 int gmmsp_ws_attach(gmmsp_handle* h, void* ws_dev, size_t bytes, void* stream) {
   if (!h || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
-  if (h->P.cov3) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
+  if (h->P.cov_mode != 0) return fail(GMMSP_E_INVAL, "the warm start predicts the split colour blocks (cov_mode 0)");
   if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
   const WsLayoutSizes z = ws_sizes(h);
   if (bytes < z.total) return fail(GMMSP_E_SIZE, "warm-start workspace %zu < %zu bytes", bytes, z.total);

@@ -21,6 +21,28 @@ constexpr int kRec3 = 20;          // floats per cell-slot record
 constexpr int kStats3 = 15;        // N, S1 (5), S2 (xx xy yy LL La Lb aa ab bb)
 constexpr int kPart3 = 136;        // doubles per cell: 9 x 15 statistics, 1 pad
 constexpr int kThetaRow3 = 15;     // doubles per superpixel in the FP64 master
+// the full 5 x 5 Sigma (cov_mode 2)
+constexpr int kRecF = 24;          // floats per cell-slot record
+constexpr int kStatsF = 21;        // N, S1 (5), S2 (15)
+constexpr int kPartF = 192;        // doubles per cell: 9 x 21 statistics, 3 pad
+constexpr int kThetaRowF = 21;     // mu (5), Sigma upper triangle (15), N
+// grayscale images, D = 3 (cov_mode 3)
+constexpr int kRecG = 12;          // floats per cell-slot record
+constexpr int kStatsG = 8;         // N, S1 (x y I), S2 (xx xy yy II)
+constexpr int kPartG = 72;         // doubles per cell: 9 x 8 statistics
+constexpr int kThetaRowG = 8;      // mu (3), Sxx Sxy Syy SII, N
+// the partials of one cell wave fit every model (the split model has kMaxWpc
+// sets of kPartStride per cell, the others one set)
+static_assert(kPart3 <= kPartStride * kMaxWpc && kPartF <= kPartStride * kMaxWpc, "partials");
+
+// FP64 master row and record sizes of a covariance model
+inline int theta_row_of(int cov_mode) {
+  return cov_mode == 0 ? kThetaRow : cov_mode == 1 ? kThetaRow3 : cov_mode == 2 ? kThetaRowF
+                                                                                : kThetaRowG;
+}
+inline int rec_floats_of(int cov_mode) {
+  return cov_mode == 0 ? kRecFloats : cov_mode == 1 ? kRec3 : cov_mode == 2 ? kRecF : kRecG;
+}
 
 // Cell-slot record: the parameters of the superpixel in slot s of cell c, in
 // float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
@@ -82,7 +104,8 @@ struct DevPtrs {
   int32_t* n_done;          // images that have stopped
   int32_t n_img, n_cell, n_sp;
   int32_t wpc;              // waves per cell of the statistics pass (1, 2 or 4)
-  int32_t cov3;             // 1: the 3x3 colour block (cov_mode 1), kernels of gmmsp_cov3.hip
+  int32_t cov_mode;         // 0 split colour blocks; 1 3x3 colour block (gmmsp_cov3.hip);
+                            // 2 full 5x5, 3 grayscale (gmmsp_modes.hip)
 };
 
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
@@ -98,14 +121,23 @@ hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStre
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
 
 // The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
-// 2 responsibilities, 3 candidates.  The launchers above dispatch to these
-// when P.cov3 is set.
+// 2 responsibilities, 3 candidates.
 hipError_t launch3_clear_records(const DevPtrs& P, hipStream_t s);
 hipError_t launch3_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s);
 hipError_t launch3_set_params(const DevPtrs& P, const double* rows, hipStream_t s);
 hipError_t launch3_cells(const DevPtrs& P, int mode, const float* lab, int32_t* out_i,
                          float* out_f, hipStream_t s);
 hipError_t launch3_finalize(const DevPtrs& P, hipStream_t s);
+
+// Every covariance model but the split colour blocks (gmmsp_modes.hip: the
+// full 5x5 and grayscale kernels, and the 3x3 block's above); same modes.  The
+// launchers of gmmsp_kernels.hip dispatch to these when P.cov_mode != 0.
+hipError_t launch_alt_clear_records(const DevPtrs& P, hipStream_t s);
+hipError_t launch_alt_init_seeds(const DevPtrs& P, const float* in, hipStream_t s);
+hipError_t launch_alt_set_params(const DevPtrs& P, const double* rows, hipStream_t s);
+hipError_t launch_alt_cells(const DevPtrs& P, int mode, const float* in, int32_t* out_i,
+                            float* out_f, hipStream_t s);
+hipError_t launch_alt_finalize(const DevPtrs& P, hipStream_t s);
 
 // Warm-start network launchers (gmmsp_warmstart.hip).
 hipError_t ws_launch_nbr(const DevPtrs& P, int32_t* nbr, hipStream_t s);

@@ -715,7 +715,7 @@ static inline unsigned blocks_for(size_t n, unsigned per) {
 }
 
 hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s) {
-  if (P.cov3) return launch3_clear_records(P, s);
+  if (P.cov_mode) return launch_alt_clear_records(P, s);
   const size_t n = (size_t)P.n_cell * kSlots;
   hipLaunchKernelGGL(k_clear_records, dim3(blocks_for(n, 256)), dim3(256), 0, s, P.rec, n);
   return hipGetLastError();
@@ -727,19 +727,19 @@ hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s) {
 }
 
 hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s) {
-  if (P.cov3) return launch3_init_seeds(P, lab, s);
+  if (P.cov_mode) return launch_alt_init_seeds(P, lab, s);
   hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab);
   return hipGetLastError();
 }
 
 hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s) {
-  if (P.cov3) return launch3_set_params(P, rows, s);
+  if (P.cov_mode) return launch_alt_set_params(P, rows, s);
   hipLaunchKernelGGL(k_set_params, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, rows);
   return hipGetLastError();
 }
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
-  if (P.cov3) return launch3_cells(P, 0, lab, nullptr, nullptr, s);
+  if (P.cov_mode) return launch_alt_cells(P, 0, lab, nullptr, nullptr, s);
   const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
   if (P.wpc == 4)
     hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
@@ -759,14 +759,14 @@ hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
-  if (P.cov3) return launch3_finalize(P, s);
+  if (P.cov_mode) return launch_alt_finalize(P, s);
   hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s) {
-  if (P.cov3) {
-    const hipError_t e = launch3_cells(P, 1, lab, labels, nullptr, s);
+  if (P.cov_mode) {
+    const hipError_t e = launch_alt_cells(P, 1, lab, labels, nullptr, s);
     if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
@@ -777,14 +777,14 @@ hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hip
 }
 
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s) {
-  if (P.cov3) return launch3_cells(P, 2, lab, nullptr, R, s);
+  if (P.cov_mode) return launch_alt_cells(P, 2, lab, nullptr, R, s);
   hipLaunchKernelGGL(k_cells<M_EXPORT_R>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256),
                      0, s, P, lab, (int32_t*)nullptr, R);
   return hipGetLastError();
 }
 
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s) {
-  if (P.cov3) return launch3_cells(P, 3, nullptr, cand, nullptr, s);
+  if (P.cov_mode) return launch_alt_cells(P, 3, nullptr, cand, nullptr, s);
   hipLaunchKernelGGL(k_cells<M_EXPORT_CAND>, dim3(blocks_for(P.n_cell, kWavesPerBlock)),
                      dim3(256), 0, s, P, (const float*)nullptr, cand, (float*)nullptr);
   return hipGetLastError();

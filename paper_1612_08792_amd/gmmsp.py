@@ -63,7 +63,10 @@ class GMMSP:
             arr[b] = make_params(W, H, Ks[b] or 0, vx, vy, eps_s, eps_c, lam, cov_mode, n_min)
         self.params = arr
         self.cov_mode = cov_mode
-        self.theta_row = _lib.THETA_ROW3 if cov_mode == 1 else _lib.THETA_ROW
+        if cov_mode not in _lib.THETA_ROWS:
+            raise ValueError("cov_mode must be 0, 1, 2 or 3")
+        self.theta_row = _lib.THETA_ROWS[cov_mode]
+        self.channels = 1 if cov_mode == 3 else 3   # grayscale: one float per pixel
         self.n_images = n
         self.device = torch.device(device)
         nbytes = c_size_t(0)
@@ -90,11 +93,12 @@ class GMMSP:
     def _stream(self) -> int:
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def _lab(self, lab: torch.Tensor) -> c_void_p:
+    def _lab(self, lab: torch.Tensor, channels: int | None = None) -> c_void_p:
+        ch = self.channels if channels is None else channels
         if lab.dtype != torch.float32 or not lab.is_contiguous() or lab.device != self.device:
             raise ValueError("lab must be a contiguous float32 tensor on the handle's device")
-        if lab.numel() != 3 * self.n_pixels:
-            raise ValueError(f"lab has {lab.numel()} floats, expected {3 * self.n_pixels}")
+        if lab.numel() != ch * self.n_pixels:
+            raise ValueError(f"lab has {lab.numel()} floats, expected {ch * self.n_pixels}")
         return c_void_p(_ptr(lab))
 
     def close(self):
@@ -317,7 +321,7 @@ class GMMSP:
         if ws is None or ws.numel() < nbytes.value:
             ws = self.conn_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         counts = np.zeros((self.n_images, 4), dtype=np.int32)
-        check(lib().gmmsp_connectivity(self.handle, self._lab(lab), c_void_p(_ptr(labels)),
+        check(lib().gmmsp_connectivity(self.handle, self._lab(lab, 3), c_void_p(_ptr(labels)),
                                        c_void_p(_ptr(out)), c_void_p(_ptr(ws)), nbytes.value,
                                        1 if compact else 0, c_void_p(counts.ctypes.data),
                                        c_void_p(self._stream())))

@@ -94,12 +94,18 @@ def test_workspace_bytes_and_validation():
     n1 = c_size_t(0)
     assert L.gmmsp_workspace_bytes(1, arr, byref(n1)) == 0
     assert n.value > n1.value > 154401 // 10
-    bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, cov_mode=2))
-    assert L.gmmsp_workspace_bytes(1, bad, byref(n)) == _lib.GMMSP_E_INVAL
-    # the 3x3 colour block needs wider records and rows; one cov_mode per batch
-    c3 = (_lib.GmmspParams * 1)(make_params(481, 321, 400, cov_mode=1))
-    n3 = c_size_t(0)
-    assert L.gmmsp_workspace_bytes(1, c3, byref(n3)) == 0 and n3.value > n1.value
+    for m in (-1, 4):
+        bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, cov_mode=m))
+        assert L.gmmsp_workspace_bytes(1, bad, byref(n)) == _lib.GMMSP_E_INVAL
+    # the 3x3 colour block and the full Sigma need wider records and rows, the
+    # grayscale model narrower ones; one cov_mode per batch
+    sizes = {}
+    for m in (0, 1, 2, 3):
+        arr_m = (_lib.GmmspParams * 1)(make_params(481, 321, 400, cov_mode=m))
+        nm = c_size_t(0)
+        assert L.gmmsp_workspace_bytes(1, arr_m, byref(nm)) == 0
+        sizes[m] = nm.value
+    assert sizes[3] < sizes[0] < sizes[1] < sizes[2]
     mixed = (_lib.GmmspParams * 2)(make_params(481, 321, 400), make_params(481, 321, 400, cov_mode=1))
     assert L.gmmsp_workspace_bytes(2, mixed, byref(n)) == _lib.GMMSP_E_INVAL
     bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, eps_c=0.0))
