@@ -1,5 +1,5 @@
 // Internal layout shared by the host API (gmmsp_api.cpp) and the kernels
-// (gmmsp_kernels.hip).  Not part of the public ABI.
+// (gmmsp_*.hip).  Not part of the public ABI.
 #pragma once
 
 #include <stdint.h>

@@ -1,6 +1,6 @@
 // Device helpers shared by the per-cell kernels (gmmsp_kernels.hip,
-// gmmsp_cov3.hip): scalar-load pointers, FP64 constants and the wave-wide
-// butterfly reduce-scatter.  Not part of the public ABI.
+// gmmsp_cov3.hip, gmmsp_modes.hip): scalar-load pointers, FP64 constants and
+// the wave-wide butterfly reduce-scatter.  Not part of the public ABI.
 #pragma once
 
 #include "gmmsp_internal.h"
