@@ -3,8 +3,10 @@ ground-truth region maps: boundary recall, under-segmentation error (Eq. ue)
 and achievable segmentation accuracy (Eq. asa), before and after the
 connectivity post-processing, for the paper's setting (T = 10, lambda = 8,
 eps_c = 8), for EM run to the 1e-5 stop rule from the grid and from the
-learned warm start, and for sweeps of lambda and eps_c (Sec. IV, effect of
-lambda and eps_c) at T = 10.
+learned warm start, for sweeps of lambda and eps_c (Sec. IV, effect of
+lambda and eps_c) at T = 10, and for the other covariance models at T = 10:
+the 3x3 colour block, the full 5x5 Sigma (Sec. III-B holds that full matrices
+do not improve accuracy), and the L channel alone as a grayscale image.
 
     python -m paper_1612_08792_amd.quality [--images 256] [--K 400]
 
@@ -29,8 +31,9 @@ from paper_1612_08792_amd import train_warmstart, warmstart  # noqa: E402
 from paper_1612_08792_amd.gmmsp import GMMSP  # noqa: E402
 
 
-def measure(m: GMMSP, lab, gt, n_regions):
-    labels, _ = m.label(lab)
+def measure(m: GMMSP, x, lab, gt, n_regions):
+    """x: the EM input; lab: the three channels the connectivity step compares."""
+    labels, _ = m.label(x)
     raw, _ = m.metrics(labels, gt, n_regions)
     comp, counts = m.connectivity(lab, labels, compact=True)
     con, _ = m.metrics(comp, gt, n_regions, n_sp=counts[:, 3])
@@ -52,14 +55,22 @@ def main():
     n_regions = 40
     rows = []
 
-    def run(name, lam=8.0, eps_c=8.0, T=10, tol=0.0, warm=None):
-        m = GMMSP(sizes, K=args.K, lam=lam, eps_c=eps_c, device=dev)
+    # grayscale: the L channel; the connectivity step compares (L, 0, 0)
+    lab3 = lab.reshape(-1, 3)
+    gray = lab3[:, 0].contiguous()
+    gray3 = torch.zeros_like(lab3)
+    gray3[:, 0] = gray
+
+    def run(name, lam=8.0, eps_c=8.0, T=10, tol=0.0, warm=None, cov_mode=0):
+        m = GMMSP(sizes, K=args.K, lam=lam, eps_c=eps_c, device=dev, cov_mode=cov_mode)
+        x, xc = (gray, gray3.reshape(-1)) if cov_mode == 3 else (lab, lab)
         if warm is not None:
             warmstart.warm_start(m, lab, warm, train_warmstart.MASK)
         else:
-            m.init_seeds(lab)
-        it = m.em_iterate(lab, T, tol)
-        r = dict(setting=name, lam=lam, eps_c=eps_c, passes=float(np.mean(it)), **measure(m, lab, gt, n_regions))
+            m.init_seeds(x)
+        it = m.em_iterate(x, T, tol)
+        r = dict(setting=name, lam=lam, eps_c=eps_c, passes=float(np.mean(it)),
+                 **measure(m, x, xc, gt, n_regions))
         print(json.dumps(r), flush=True)
         rows.append(r)
 
@@ -71,6 +82,9 @@ def main():
         run(f"lambda = {lam:g}, T = 10", lam=lam)
     for eps_c in (2.0, 4.0, 16.0, 32.0):
         run(f"eps_c = {eps_c:g}, T = 10", eps_c=eps_c)
+    run("3x3 colour block (cov_mode 1), T = 10", cov_mode=1)
+    run("full 5x5 Sigma (cov_mode 2), T = 10", cov_mode=2)
+    run("grayscale L only (cov_mode 3), T = 10", cov_mode=3)
     print("| setting | passes | BR | UE | ASA | BR conn. | UE conn. | ASA conn. | segments conn. |")
     print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
     for r in rows:
