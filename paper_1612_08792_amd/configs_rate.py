@@ -1,0 +1,103 @@
+"""Per-iteration rates of the EM on the benchmark workloads, paper T mode (a
+fixed number of iterations, Algorithm 1): 481x321 (K 400, T = 10), 1920x1080
+(K 2000, T = 20), the uneven batch of 64 images (T = 15) and the 4K batch
+(32 x 3840x2160, K 10000, T = 10).  Each workload is autotuned (waves per
+cell), then timed with graph replay:
+
+  * Mpix/s per iteration = total pixels x iterations / wall time of the
+    iterations (E-step, statistics, gather, LL and stop rule; inputs resident);
+  * the E-step alone (one more, eager run): HIP-event time of its launches on
+    the launch stream, Gpx/s per pass and TFLOP/s of the 54 algorithmic flops per (pixel,
+    candidate) pair, against the 78.6 TFLOP/s one-FMA-per-lane FP32 roof.
+
+    python -m paper_1612_08792_amd.configs_rate [--configs 1,2,3,5] [--repeats 5]
+
+Prints one JSON line per workload and a markdown table."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_1612_08792_amd.gmmsp import GMMSP  # noqa: E402
+
+PEAK_FP32 = 78.6    # TFLOP/s, one FP32 FMA per lane (256 CU x 4 SIMD x 16 x 2 x 2.4 GHz)
+FLOPS_PER_PAIR = 54.0
+
+
+def workload(c: int, dev):
+    if c == 1:
+        return "481x321, K 400, T 10", [synth.config1_image(dev)], 10
+    if c == 2:
+        return "1920x1080, K 2000, T 20", [synth.config2_image(dev)], 20
+    if c == 3:
+        return "64 uneven images, T 15", synth.config3_batch(dev), 15
+    return "32 x 3840x2160, K 10000, T 10", synth.config5_batch(dev), 10
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--configs", type=str, default="1,2,3,5")
+    ap.add_argument("--repeats", type=int, default=5)
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    rows = []
+    for c in (int(x) for x in args.configs.split(",")):
+        name, ims, T = workload(c, dev)
+        lab = synth.pack_batch(ims).contiguous()
+        m = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
+        wpc = m.autotune(lab, passes=3, cache=None)
+        m.set_graph_passes(T)
+        m.init_seeds(lab)
+        m.em_iterate(lab, T)                        # warm-up (graph capture)
+        walls = []
+        for _ in range(args.repeats):
+            m.init_seeds(lab)
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            m.em_iterate(lab, T)
+            torch.cuda.synchronize(dev)
+            walls.append(time.perf_counter() - t0)
+        # the E-step alone: an eager run with events around each launch (the
+        # library replays no graph while it profiles)
+        m.profile(True)
+        m.profile_read(True)
+        m.init_seeds(lab)
+        m.em_iterate(lab, T)
+        p = m.profile_read(True)
+        m.profile(False)
+        t = float(np.median(walls))
+        est = p["estep_ms"] / p["launches"]
+        tflops = p["pair_evals"] * FLOPS_PER_PAIR / (p["estep_ms"] / 1e3) / 1e12
+        r = dict(config=c, workload=name, images=len(ims), pixels=m.n_pixels, T=T,
+                 waves_per_cell=wpc, mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
+                 ms_per_iteration=round(1e3 * t / T, 4), estep_ms_per_launch=round(est, 4),
+                 estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
+                 pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),
+                 estep_tflops=round(tflops, 2), frac_of_78_6=round(tflops / PEAK_FP32, 3))
+        print(json.dumps(r), flush=True)
+        rows.append(r)
+        m.close()
+        del m, lab, ims
+        torch.cuda.empty_cache()
+    print("| workload | Mpix/s per iteration | ms per iteration | E-step us | E-step Gpx/s | "
+          "TFLOP/s | of 78.6 | waves per cell |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        print(f"| {r['workload']} | {r['mpix_per_s_per_iteration']:.0f} | {r['ms_per_iteration']:.3f} | "
+              f"{1e3 * r['estep_ms_per_launch']:.0f} | {r['estep_gpx_per_s']:.1f} | "
+              f"{r['estep_tflops']:.1f} | {r['frac_of_78_6']:.2f} | {r['waves_per_cell']} |")
+
+
+if __name__ == "__main__":
+    main()
