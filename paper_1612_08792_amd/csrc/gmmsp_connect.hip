@@ -47,17 +47,22 @@ constexpr int kT = 256;
 constexpr int kScanPer = 16;                // elements per thread of the scan
 constexpr int kScanBlock = kScanPer * 256;  // elements per block of the scan
 
-__device__ __forceinline__ int ld_acq(const int* p) {
+// loads and stores of state other threads update (device-coherent: served by
+// the L2, never by a possibly stale L1 line)
+__device__ __forceinline__ int ld_dev(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // root of x in a forest with parent[x] <= x (every link points to a smaller
 // index, so the walk strictly decreases and ends)
 __device__ int uf_find(int* par, int x) {
-  int y = ld_acq(par + x);
+  int y = ld_dev(par + x);
   while (y != x) {
     x = y;
-    y = ld_acq(par + x);
+    y = ld_dev(par + x);
   }
   return x;
 }
@@ -108,10 +113,10 @@ __device__ double colour_dist2(const double* a, const double* b) {
 
 // merge parent walk: a segment points to the segment it was merged into
 __device__ __forceinline__ int m_find(const int* mpar, int t) {
-  int u = mpar[t];
+  int u = ld_dev(mpar + t);
   while (u != t) {
     t = u;
-    u = mpar[t];
+    u = ld_dev(mpar + t);
   }
   return t;
 }
@@ -244,8 +249,8 @@ __global__ __launch_bounds__(128) void k_cc_border(const ImgDesc* img, const int
     if (in) {
       a = labels[i];
       c = labels[i - W];
-      ra = ld_acq(par + i);
-      rc = ld_acq(par + i - W);
+      ra = ld_dev(par + i);
+      rc = ld_dev(par + i - W);
     }
   } else {  // first column against the last column of the tile on the left
     if (x0 == 0) return;
@@ -657,12 +662,12 @@ __device__ __forceinline__ void scan_pixel(int j, int W, int H, int off, int s, 
 __device__ __forceinline__ void merge_into(const ImgDesc* img, const int* seg_img, const int* size0,
                                            int s, int best, int* size, int* mpar, int* next,
                                            int* tail) {
-  mpar[s] = best;
-  atomicAdd(size + best, size[s]);
-  size[s] = 0;
+  st_dev(mpar + s, best);
+  atomicAdd(size + best, ld_dev(size + s));  // a large destination is shared by clusters
+  st_dev(size + s, 0);
   if (is_small(img, seg_img, size0, best)) {
-    next[tail[best]] = s;
-    tail[best] = tail[s];
+    st_dev(next + ld_dev(tail + best), s);
+    st_dev(tail + best, ld_dev(tail + s));
   }
 }
 
@@ -687,11 +692,11 @@ __device__ void merge_cluster(const ImgDesc* img, int r, const int* seg_img, con
   const int64_t desired = (int64_t)I.vx * I.vy;
   for (int q = 0; q < n; ++q) {
     const int s = v[q];
-    if (4LL * size[s] >= desired) continue;
+    if (4LL * ld_dev(size + s) >= desired) continue;
     const double* ms = mean + 3 * (int64_t)s;
     int best = -1;
     double bd = 0.0;
-    for (int m = s; m >= 0; m = next[m]) {
+    for (int m = s; m >= 0; m = ld_dev(next + m)) {
       const int p0 = poff[m], np = size0[m];
       for (int u = 0; u < np; ++u)
         scan_pixel(plist[p0 + u] - off, W, H, off, s, ms, segid, mpar, mean, best, bd);
@@ -777,11 +782,11 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_merge_big(
     const int64_t desired = (int64_t)I.vx * I.vy;
     for (int q = 0; q < n; ++q) {
       const int s = (int)(unsigned)(kw[q] & 0xFFFFFFFFull);
-      if (4LL * size[s] >= desired) continue;
+      if (4LL * ld_dev(size + s) >= desired) continue;
       const double* ms = mean + 3 * (int64_t)s;
       int best = -1;
       double bd = 0.0;
-      for (int m = s; m >= 0; m = next[m]) {
+      for (int m = s; m >= 0; m = ld_dev(next + m)) {
         const int p0 = poff[m], np = size0[m];
         for (int u = lane; u < np; u += 64)
           scan_pixel(plist[p0 + u] - off, W, H, off, s, ms, segid, mpar, mean, best, bd);
@@ -797,10 +802,10 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_merge_big(
       }
       if (best < 0) continue;  // every lane holds the same result
       if (lane == 0) merge_into(img, seg_img, size0, s, best, size, mpar, next, tail);
-      // lane 0's writes, seen by every lane's reads of the next visit
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // lane 0's stores complete before any lane's next (L2-served) reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
   }
 }
