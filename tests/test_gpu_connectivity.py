@@ -118,6 +118,29 @@ def test_long_components_across_tiles(dev):
     check_exact(dev, items, 8)
 
 
+def test_degenerate_shapes(dev):
+    """Images one pixel wide or tall, a single pixel, and thin strips that cross
+    the 64-pixel tile borders, in one uneven batch; the seed spacing (vx, vy) of
+    each keeps its grid valid while single pixels still count as small."""
+    rng = np.random.default_rng(19)
+    cases = [((50, 1), (1, 8)), ((1, 70), (8, 1)), ((1, 1), (1, 1)), ((2, 130), (8, 2)),
+             ((130, 2), (2, 8)), ((65, 65), (4, 4))]            # (H, W), (vx, vy)
+    items = [(rng.integers(0, 3, hw), rng.uniform(0, 100, (*hw, 3)).astype(np.float32))
+             for hw, _ in cases]
+    m = GMMSP([(l.shape[1], l.shape[0]) for l, _ in items], v=[v for _, v in cases], device=dev)
+    labels = torch.from_numpy(np.concatenate([l.astype(np.int32).ravel() for l, _ in items])).to(dev)
+    lab = torch.from_numpy(np.concatenate([x.reshape(-1) for _, x in items])).to(dev)
+    out, counts = m.connectivity(lab, labels)
+    out = out.cpu().numpy()
+    merged = 0
+    for b, ((l, x), (_, (vx, vy))) in enumerate(zip(items, cases)):
+        want, info = C.enforce_connectivity(l, x, vx, vy)
+        assert np.array_equal(out[m.image_slice(b)].reshape(l.shape), want), b
+        assert list(counts[b]) == [info["segments"], info["small"], info["merged"], info["final"]], b
+        merged += info["merged"]
+    assert merged > 0
+
+
 def test_hand_cases(dev):
     # inherited neighbours: A joins B, B then joins Y through A's pixel
     labels = np.zeros((10, 10), np.int64)

@@ -104,6 +104,23 @@ def test_many_region_ids_and_fragmented_labels(dev):
     check(vals, sums, M.metrics(sp, gt), 0)
 
 
+def test_degenerate_shapes(dev):
+    """One-pixel-wide and -tall images, a single pixel and strips crossing the
+    64 x 16 tiles of the pixel pass, in one uneven batch."""
+    rng = np.random.default_rng(23)
+    shapes = [(1, 50), (70, 1), (1, 1), (130, 2), (2, 40), (65, 17)]   # W, H
+    sp_maps, gt_maps = [], []
+    for W, H in shapes:
+        sp_maps.append(rng.integers(0, 1, (H, W)) if W * H == 1 else rng.integers(0, 2, (H, W)))
+        gt_maps.append(rng.integers(0, 3, (H, W)))
+    # K = W H: a seed spacing of 1, a valid grid for any shape
+    (vals, sums), m = gpu_metrics(dev, shapes, [W * H for W, H in shapes], sp_maps, gt_maps,
+                                  [3] * len(shapes))
+    for b in range(len(shapes)):
+        assert m.grids[b].K >= 1
+        check(vals, sums, M.metrics(sp_maps[b], gt_maps[b]), b)
+
+
 def test_out_of_range_values_are_an_error(dev):
     W, H = 30, 20
     sp = np.zeros((H, W), np.int64)
