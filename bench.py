@@ -14,7 +14,8 @@ run, with the plain one beside it.
 Prints one JSON line.  The dominant kernel (the fused E-step / statistics pass)
 is timed live with HIP events on the launch stream by the library; its
 roofline is FP32 ALU arithmetic (54 algorithmic flops per (pixel, candidate)
-pair).  The CPU baseline times the FP64 oracle on a bounded sample.
+pair).  The CPU baseline times the FP64 oracle on a bounded sample: one EM pass
+on each of up to 16 images, one single-threaded process per image.
 """
 import argparse
 import hashlib
@@ -81,32 +82,55 @@ def load_or_train_weights(dev):
     return params
 
 
-def cpu_baseline(lab_img, W, H, K, iters_mean):
-    """FP64 oracle: one EM pass (E-step + M-step) over one full image of the
-    batch, extrapolated to the mean number of passes the GPU needed (+1 E-step
-    for the labels)."""
-    import numpy as np
+def _oracle_pass(job):
+    """One FP64 oracle EM pass (set-up, E-step, M-step) over one image; runs in
+    a worker process.  Returns the three times and the grid size."""
+    lab, W, H, K = job
     from oracle import gmm_oracle as O
-    g = O.make_grid(W, H, K=K)
-    lab = lab_img.cpu().numpy().reshape(H, W, 3)
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
-    z = O.features(lab)
+    g = O.make_grid(W, H, K=K)
+    z = O.features(lab.reshape(H, W, 3))
     cand, _ = O.candidate_sets(g)
     pos = O.window_positions(g, cand)
     th = O.init_theta(g, z, O.Params())
     t1 = time.perf_counter()
-    R, _, L = O.estep(z, cand, th)
+    R, _, _ = O.estep(z, cand, th)
     t2 = time.perf_counter()
     O.mstep(z, g, R, pos, th, O.Params())
     t3 = time.perf_counter()
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    return t1 - t0, t2 - t1, t3 - t2, g.K
+
+
+def cpu_baseline(labs, W, H, K, iters_mean, workers):
+    """FP64 oracle on `workers` images of the batch at once, one single-threaded
+    process per image on the host's cores: one EM pass each, extrapolated to the
+    mean number of passes the GPU needed (+1 E-step for the labels)."""
+    import multiprocessing
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                            "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"             # one thread per worker process
+    try:
+        ctx = multiprocessing.get_context("spawn")
+        r0 = resource.getrusage(resource.RUSAGE_CHILDREN)
+        t0 = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_oracle_pass, [(lab, W, H, K) for lab in labs[:workers]])
+        wall = time.perf_counter() - t0
+        r1 = resource.getrusage(resource.RUSAGE_CHILDREN)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    wall = t3 - t0
-    t_pass = t3 - t1
-    t_e = t2 - t1
     npx = W * H
-    t_conv = (t1 - t0) + t_pass * iters_mean + t_e
+    # each image to convergence; the sample's images run side by side
+    t_conv = max(su + (te + tm) * iters_mean + te for su, te, tm, _ in res)
+    t_e = max(r[1] for r in res)
+    t_m = max(r[2] for r in res)
+    t_su = max(r[0] for r in res)
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -114,16 +138,18 @@ def cpu_baseline(lab_img, W, H, K, iters_mean):
     except OSError:
         pass
     return {
-        "value": round(npx / t_conv / 1e6, 4),
+        "value": round(workers * npx / t_conv / 1e6, 4),
         "unit": "Mpix/s",
-        "cores": max(1, int(round(cpu_s / wall))),
+        "cores": workers,
         "kind": "oracle",
         "cpu_model": model,
         "host_cores_available": len(os.sched_getaffinity(0)),
-        "sample": (f"FP64 oracle, one EM pass (E-step {t_e:.1f} s + M-step {t3 - t2:.1f} s) "
-                   f"plus set-up {t1 - t0:.1f} s on image 0 ({W}x{H}, K={g.K}); to-convergence "
-                   f"time extrapolated to the GPU's mean {iters_mean:.1f} passes + 1 labelling "
-                   f"E-step; per-pass rate {npx / t_pass / 1e6:.3f} Mpix/s"),
+        "cpu_busy_cores_measured": round(cpu_s / wall, 1),
+        "sample": (f"FP64 oracle, one EM pass on each of images 0..{workers - 1} ({W}x{H}, "
+                   f"K={res[0][3]}) in {workers} single-threaded processes side by side "
+                   f"(slowest: E-step {t_e:.1f} s, M-step {t_m:.1f} s, set-up {t_su:.1f} s); "
+                   f"to-convergence time of each image extrapolated to the GPU's mean "
+                   f"{iters_mean:.1f} passes + 1 labelling E-step"),
     }
 
 
@@ -136,6 +162,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--cap", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes of the CPU baseline (default: the host's cores, "
+                         "at most 16 and at most the number of images)")
     ap.add_argument("--mode", choices=("both", "plain", "warm"), default="both")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run three plain device copies of this many MiB, the "
@@ -300,8 +329,11 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         plain_iters = runs["plain"]["iters"] if "plain" in runs else iters
-        out["cpu_baseline"] = cpu_baseline(lab[:3 * ims[0].W * ims[0].H], ims[0].W, ims[0].H, K_req,
-                                           float(plain_iters[:, 0].mean()))
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)), len(ims))
+        npx = ims[0].W * ims[0].H
+        labs = [lab[3 * npx * b:3 * npx * (b + 1)].cpu().numpy() for b in range(workers)]
+        out["cpu_baseline"] = cpu_baseline(labs, ims[0].W, ims[0].H, K_req,
+                                           float(plain_iters[:, 0].mean()), workers)
     print(json.dumps(out), flush=True)
 
 
