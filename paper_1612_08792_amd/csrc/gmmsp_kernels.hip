@@ -199,44 +199,6 @@ __global__ __launch_bounds__(256) void k_set_params(DevPtrs P, const double* __r
 
 enum CellMode { M_STATS = 0, M_LABEL = 1, M_EXPORT_R = 2, M_EXPORT_CAND = 3 };
 
-// The five offsets of a record (o1, o2, oL, o3, o4) each enter an FMA whose
-// other two operands are a record factor and a pixel value; an FMA reads at
-// most one scalar register, so the stats kernel copies them to vector
-// registers once per cell instead of once per round.
-struct VOff {
-  float o[kSlots][5];
-};
-
-__device__ __forceinline__ void load_voff(const AS4 float* rec, VOff& v) {
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const AS4 float* f = rec + s * kRecFloats;
-    const float x[5] = {f[R_O1], f[R_O2], f[R_OL], f[R_O3], f[R_O4]};
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      float y = x[j];
-      asm volatile("" : "+v"(y));  // keep the copy in a vector register
-      v.o[s][j] = y;
-    }
-  }
-}
-
-// log2 p(z; theta_k) - cmax2 with the offsets from vector registers
-__device__ __forceinline__ float eval_l_v(const AS4 float* f, const float (&o)[5], float xr,
-                                          float yr, float L, float A, float B) {
-  const float t1 = fmaf(f[R_L11], xr, fmaf(f[R_L12], yr, o[0]));
-  const float t2 = fmaf(f[R_L22], yr, o[1]);
-  const float w = fmaf(f[R_SL], L, o[2]);
-  const float u1 = fmaf(f[R_A11], A, fmaf(f[R_A12], B, o[3]));
-  const float u2 = fmaf(f[R_A22], B, o[4]);
-  float l = fmaf(-t1, t1, f[R_C]);
-  l = fmaf(-t2, t2, l);
-  l = fmaf(-w, w, l);
-  l = fmaf(-u1, u1, l);
-  l = fmaf(-u2, u2, l);
-  return l;
-}
-
 // log2 p(z; theta_k) - cmax2 for the record at f (Eq. gaussian, block diagonal)
 __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, float L,
                                         float A, float B) {
@@ -253,31 +215,13 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
   return l;
 }
 
-// record offsets held in vector registers for the whole cell (see VOff)
-#ifndef GMMSP_VOFF
-#define GMMSP_VOFF 0
-#endif
-
 // 3 waves per SIMD measured fastest for the statistics pass (168 VGPRs)
-#ifndef GMMSP_WAVES_PER_EU
-#define GMMSP_WAVES_PER_EU 3
-#endif
-#if GMMSP_WAVES_PER_EU > 0
-#define CELLS_ATTR __attribute__((amdgpu_waves_per_eu(GMMSP_WAVES_PER_EU)))
-#else
-#define CELLS_ATTR
-#endif
+#define CELLS_ATTR __attribute__((amdgpu_waves_per_eu(3)))
 
 // E-step of NP pixels per lane against the nine records of the wave's cell:
 // e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
 // shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
 // Each record value is read once (scalar load) for all NP pixels.
-#ifndef GMMSP_MOV64
-#define GMMSP_MOV64 1
-#endif
-#ifndef GMMSP_JOINT
-#define GMMSP_JOINT 1
-#endif
 typedef float f2v __attribute__((ext_vector_type(2)));
 
 // log2 p(z; theta_k) - cmax2 with the five offsets in vector registers
@@ -297,22 +241,19 @@ __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2
   return l;
 }
 
-template <int NP, bool VO = false>
+template <int NP>
 __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (&xr)[NP],
                                              const float (&yr)[NP], const float (&L)[NP],
                                              const float (&A)[NP], const float (&B)[NP],
                                              float (&e)[NP][kSlots], float (&sum)[NP],
-                                             float (&shift)[NP], const VOff* vo = nullptr) {
+                                             float (&shift)[NP]) {
 #pragma unroll
   for (int p = 0; p < NP; ++p) sum[p] = 0.f;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const AS4 float* f = rec + s * kRecFloats;
     float l[NP];
-    if constexpr (VO) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p) l[p] = eval_l_v(f, vo->o[s], xr[p], yr[p], L[p], A[p], B[p]);
-    } else if constexpr (GMMSP_MOV64 && NP > 1) {
+    if constexpr (NP > 1) {
       // An FMA reads at most one scalar register, so each offset (the addend
       // beside a scalar record factor) must sit in a vector register: copy
       // the offsets once per slot for all NP pixels, two at a time.  (With
@@ -337,7 +278,6 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
       sum[p] += e[p][s];
     }
   }
-#if GMMSP_JOINT
   // one branch for all NP pixels, so the compiler keeps their evaluations together
   float smin = sum[0];
 #pragma unroll
@@ -348,13 +288,6 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       if (sum[p] < 0x1p-100f) {
-#else
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    shift[p] = 0.f;
-    {
-      if (sum[p] < 0x1p-100f) {
-#endif
         // every candidate is far away: subtract the largest exponent first
         float lv[kSlots];
         float m = -INFINITY;
@@ -492,10 +425,6 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     const int step = 128 * wpc;
     const int dr = step / w, dc = step - (step / w) * w;
     const int n_pair = npix > 64 ? (npix - 64 + 127) >> 7 : 0;  // rounds with base + 64 < npix
-#if GMMSP_VOFF
-    VOff vo;
-    load_voff(rec0, vo);
-#endif
     for (int rd = sub; rd < n_pair; rd += wpc) {
       const int base = rd << 7;
       // The 144 record floats do not fit the scalar registers; an opaque zero
@@ -511,11 +440,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
       const float xr[2] = {(float)c1, (float)c2}, yr[2] = {(float)r1, (float)r2};
       float e[2][kSlots], sum[2], shift[2];
-#if GMMSP_VOFF
-      estep_pixels<2, true>(rec, xr, yr, L, A, B, e, sum, shift, &vo);
-#else
       estep_pixels<2>(rec, xr, yr, L, A, B, e, sum, shift);
-#endif
       const float inv[2] = {__builtin_amdgcn_rcpf(sum[0]), v2 ? __builtin_amdgcn_rcpf(sum[1]) : 0.f};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;

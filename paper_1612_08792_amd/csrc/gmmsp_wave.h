@@ -25,28 +25,10 @@ constexpr double kLn2Pi = 1.8378770664093454836;
 // ones.  Keep bits go 5, 4, 3, 2, 1, 0: each step consumes the lowest bit of an
 // entry's index, so after the six steps lane l holds the wave total of entry
 // 64 q + bitrev6(l) at position q.
-#ifndef GMMSP_REDUCE_DPP
-#define GMMSP_REDUCE_DPP 1
-#endif
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// partner = lane ^ MASK through ds_bpermute
-template <int N, int MASK, int CAP>
-__device__ __forceinline__ void bfly_shfl(float (&v)[CAP], int lane) {
-  static_assert(2 * ((N + 1) / 2) <= CAP, "butterfly reads past the array");
-  const bool hi = (lane & MASK) != 0;
-  if (N & 1) v[N] = 0.f;  // odd count: the pair partner of the last entry is zero
-#pragma unroll
-  for (int i = 0; i < (N + 1) / 2; ++i) {
-    const float a = v[2 * i], b = v[2 * i + 1];
-    const float send = hi ? a : b;
-    const float keep = hi ? b : a;
-    v[i] = keep + __shfl_xor(send, MASK, 64);
-  }
 }
 
 // keep bit 5 (lanes 0-31 keep even entries): v_permlane32_swap exchanges the
@@ -99,21 +81,12 @@ template <int N, int CAP>
 __device__ __forceinline__ void wave_reduce_scatter(float (&v)[CAP], int lane) {
   constexpr int N1 = (N + 1) / 2, N2 = (N1 + 1) / 2, N3 = (N2 + 1) / 2, N4 = (N3 + 1) / 2,
                 N5 = (N4 + 1) / 2;
-#if GMMSP_REDUCE_DPP
   bfly_swap32<N>(v);
   bfly_swap16<N1>(v);
   bfly_dpp<N2, 3, 0x128>(v, lane);  // row_ror:8, partner lane ^ 8
   bfly_dpp<N3, 2, 0x141>(v, lane);  // row_half_mirror, partner lane ^ 7
   bfly_dpp<N4, 1, 0x4E>(v, lane);   // quad_perm [2,3,0,1], partner lane ^ 2
   bfly_dpp<N5, 0, 0xB1>(v, lane);   // quad_perm [1,0,3,2], partner lane ^ 1
-#else
-  bfly_shfl<N, 32>(v, lane);
-  bfly_shfl<N1, 16>(v, lane);
-  bfly_shfl<N2, 8>(v, lane);
-  bfly_shfl<N3, 4>(v, lane);
-  bfly_shfl<N4, 2>(v, lane);
-  bfly_shfl<N5, 1>(v, lane);
-#endif
 }
 
 }  // namespace gmmsp
