@@ -10,7 +10,7 @@ namespace gmmsp {
 
 constexpr int kSlots = 9;          // |K_i| <= 9: neighbour slots (dx, dy) in {-1,0,1}^2
 constexpr int kStats = 13;         // N, S1 (5), S2 (xx xy yy LL aa ab bb)
-constexpr int kPartStride = 120;   // doubles per cell: 9 x 13 statistics, 3 pad
+constexpr int kPartStride = 120;   // FP32 values per cell wave: 9 x 13 statistics, 3 pad
 constexpr int kRecFloats = 16;     // floats per cell-slot record
 constexpr int kThetaRow = 13;      // doubles per superpixel in the FP64 master
 constexpr int kLLCap = 4096;       // log-likelihood history entries per image
@@ -99,7 +99,9 @@ struct DevPtrs {
   const SpDesc* sp;
   double* theta;            // [n_sp][kThetaRow] FP64 master
   float* rec;               // [n_cell][9][kRecFloats]
-  double* part;             // [kMaxWpc][n_cell][kPartStride]: one set per cell wave
+  double* part;             // cell partials: split colour blocks FP32, [kMaxWpc][n_cell]
+                            // [kPartStride] (one set per cell wave); other models FP64,
+                            // one set per cell (kPart3, kPartF, kPartG doubles)
   double* llp;              // [kMaxWpc][n_cell]: log-likelihood of each cell wave's pixels
   int32_t* n_done;          // images that have stopped
   int32_t n_img, n_cell, n_sp;

@@ -461,9 +461,10 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     }
     wave_reduce_scatter<kSlots * kStats>(acc, lane);
     const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
-    double* part = P.part + ((size_t)sub * P.n_cell + cell) * kPartStride;
-    part[r] = (double)acc[0];
-    if (64 + r < kSlots * kStats) part[64 + r] = (double)acc[1];
+    // the FP32 wave totals, stored as they are; the gather adds them in FP64
+    float* part = reinterpret_cast<float*>(P.part) + ((size_t)sub * P.n_cell + cell) * kPartStride;
+    part[r] = acc[0];
+    if (64 + r < kSlots * kStats) part[64 + r] = acc[1];
   } else {
     // one pixel per lane per step of 64
     int row = lane / w, col = lane - (lane / w) * w;
@@ -586,8 +587,9 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
       // own cell origin: x' = x + ox with ox = (cx - kx) v_x
       const double ox = (double)(-dx) * I.vx, oy = (double)(-dy) * I.vy;
       for (int u = 0; u < P.wpc; ++u) {
-        const double* q = P.part + ((size_t)u * P.n_cell + I.cell_off + cy * I.ncx + cx) * kPartStride +
-                          slot * kStats;
+        const float* q = reinterpret_cast<const float*>(P.part) +
+                         ((size_t)u * P.n_cell + I.cell_off + cy * I.ncx + cx) * kPartStride +
+                         slot * kStats;
         const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
         acc[S_N] += n;
         acc[S_X] += sx + ox * n;
