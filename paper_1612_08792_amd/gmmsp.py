@@ -46,8 +46,11 @@ class GMMSP:
     """A batch of images (one image is a batch of one) bound to a workspace.
 
     ``sizes``: sequence of (W, H); ``K`` (or ``v``, an int or a (vx, vy) tuple):
-    one value for all images, or a list with one value per image.  Inputs are packed float32 Lab tensors on the device (image b
-    at pixel offset ``pix_off[b]``)."""
+    one value for all images, or a list with one value per image.  ``cov_mode``:
+    0 split colour blocks, 1 the 3x3 colour block, 2 the full 5x5 covariance,
+    3 grayscale images.  Inputs are packed float32 tensors on the device, three
+    channels (L, a, b) per pixel, one (the intensity) with cov_mode 3; image b
+    starts at pixel offset ``pix_off[b]``."""
 
     def __init__(self, sizes: Sequence[tuple], K=None, v=None, eps_s: float = 2.0,
                  eps_c: float = 8.0, lam: float = 8.0, n_min: float = 1e-3,
@@ -61,10 +64,10 @@ class GMMSP:
             vb = vs[b]
             vx, vy = (vb if isinstance(vb, (list, tuple)) else (vb, vb)) if vb else (0, 0)
             arr[b] = make_params(W, H, Ks[b] or 0, vx, vy, eps_s, eps_c, lam, cov_mode, n_min)
-        self.params = arr
-        self.cov_mode = cov_mode
         if cov_mode not in _lib.THETA_ROWS:
             raise ValueError("cov_mode must be 0, 1, 2 or 3")
+        self.params = arr
+        self.cov_mode = cov_mode
         self.theta_row = _lib.THETA_ROWS[cov_mode]
         self.channels = 1 if cov_mode == 3 else 3   # grayscale: one float per pixel
         self.n_images = n
