@@ -62,6 +62,10 @@ _SIGS = {
     "gmmsp_set_schedule": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_schedule": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_autotune": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32), c_void_p]),
+    "gmmsp_set_gather_lanes": (c_int, [c_void_p, c_int32]),
+    "gmmsp_get_gather_lanes": (c_int, [c_void_p, POINTER(c_int32)]),
+    "gmmsp_autotune_gather": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32),
+                                      c_void_p]),
     "gmmsp_set_graph_passes": (c_int, [c_void_p, c_int32]),
     "gmmsp_profile_enable": (c_int, [c_void_p, c_int32]),
     "gmmsp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_int64),

@@ -2,7 +2,8 @@
 fixed number of iterations, Algorithm 1): 481x321 (K 400, T = 10), 1920x1080
 (K 2000, T = 20), the uneven batch of 64 images (T = 15) and the 4K batch
 (32 x 3840x2160, K 10000, T = 10).  Each workload is autotuned (waves per
-cell), then timed with graph replay:
+cell of the statistics pass, lanes per superpixel of the gather), then timed
+with graph replay:
 
   * Mpix/s per iteration = total pixels x iterations / wall time of the
     iterations (E-step, statistics, gather, LL and stop rule; inputs resident);
@@ -55,6 +56,7 @@ def end_to_end(dev, repeats: int):
         ims = [synth.config4_image(20000 + i, dev) for i in range(n)]
         lab = synth.pack_batch(ims).contiguous()
         m = GMMSP([(im.W, im.H) for im in ims], K=400, device=dev)
+        m.autotune(lab, passes=3, cache=None)
         m.set_graph_passes(10)
         ts = []
         for r in range(repeats + 1):
@@ -108,7 +110,7 @@ def main():
         est = p["estep_ms"] / p["launches"]
         tflops = p["pair_evals"] * FLOPS_PER_PAIR / (p["estep_ms"] / 1e3) / 1e12
         r = dict(config=c, workload=name, images=len(ims), pixels=m.n_pixels, T=T,
-                 waves_per_cell=wpc, mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
+                 waves_per_cell=wpc, gather_lanes=m.get_gather_lanes(), mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
                  ms_per_iteration=round(1e3 * t / T, 4), estep_ms_per_launch=round(est, 4),
                  estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
                  pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),
@@ -121,12 +123,13 @@ def main():
     if 1 in [int(x) for x in args.configs.split(",")]:
         end_to_end(dev, args.repeats)
     print("| workload | Mpix/s per iteration | ms per iteration | E-step us | E-step Gpx/s | "
-          "TFLOP/s | of 78.6 | waves per cell |")
-    print("|---|---:|---:|---:|---:|---:|---:|---:|")
+          "TFLOP/s | of 78.6 | waves per cell | gather lanes |")
+    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
     for r in rows:
         print(f"| {r['workload']} | {r['mpix_per_s_per_iteration']:.0f} | {r['ms_per_iteration']:.3f} | "
               f"{1e3 * r['estep_ms_per_launch']:.0f} | {r['estep_gpx_per_s']:.1f} | "
-              f"{r['estep_tflops']:.1f} | {r['frac_of_78_6']:.2f} | {r['waves_per_cell']} |")
+              f"{r['estep_tflops']:.1f} | {r['frac_of_78_6']:.2f} | {r['waves_per_cell']} | "
+              f"{r['gather_lanes']} |")
 
 
 if __name__ == "__main__":

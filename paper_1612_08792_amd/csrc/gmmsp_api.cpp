@@ -295,6 +295,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.n_cell = L.n_cell;
   P.n_sp = L.n_sp;
   P.wpc = 1;
+  P.glanes = 1;
   P.cov_mode = L.cov_mode;
 
   hipStream_t s = (hipStream_t)stream;
@@ -612,6 +613,22 @@ int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell) {
   return GMMSP_OK;
 }
 
+int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (lanes_per_superpixel != 1 && lanes_per_superpixel != 16)
+    return fail(GMMSP_E_INVAL, "lanes per superpixel must be 1 or 16");
+  if (h->P.cov_mode != 0 && lanes_per_superpixel != 1)
+    return fail(GMMSP_E_INVAL, "cov_mode %d gathers with one lane per superpixel", h->P.cov_mode);
+  h->P.glanes = lanes_per_superpixel;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_gather_lanes(const gmmsp_handle* h, int32_t* lanes_per_superpixel) {
+  if (!h || !lanes_per_superpixel) return fail(GMMSP_E_INVAL, "null pointer");
+  *lanes_per_superpixel = h->P.glanes;
+  return GMMSP_OK;
+}
+
 int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (passes < 0 || passes > 256) return fail(GMMSP_E_INVAL, "graph passes %d outside [0, 256]", passes);
@@ -663,6 +680,54 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune");
+  h->initialised = true;
+  *chosen = pick;
+  return GMMSP_OK;
+}
+
+int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
+                          int32_t* chosen, void* stream) {
+  if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
+  if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t cand[2] = {1, 16};
+  const int n_cand = h->P.cov_mode != 0 ? 1 : 2;
+  if (ms_host)
+    for (int c = 0; c < 2; ++c) ms_host[c] = -1.0;
+  double best = 0.0;
+  int32_t pick = 1;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  for (int c = 0; c < n_cand && e == hipSuccess; ++c) {
+    h->P.glanes = cand[c];
+    // statistics of one pass from the grid seeds, then the gather timed on them
+    e = launch_reset_state(h->P, s);
+    if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+    if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
+    double tot = 0.0;
+    for (int32_t i = 0; i <= passes && e == hipSuccess; ++i) {
+      e = hipEventRecord(a, s);
+      if (e == hipSuccess) e = launch_finalize(h->P, s);
+      if (e == hipSuccess) e = hipEventRecord(b, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (i > 0) tot += ms;  // the first launch is untimed
+    }
+    if (ms_host) ms_host[c] = tot;
+    if (c == 0 || tot < best) {
+      best = tot;
+      pick = cand[c];
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  h->P.glanes = pick;
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune_gather");
   h->initialised = true;
   *chosen = pick;
   return GMMSP_OK;

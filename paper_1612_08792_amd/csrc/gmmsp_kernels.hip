@@ -567,59 +567,50 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_
 // order, mean (Eq. UpdateMu), block covariances (Eqs. UpdateSigS, UpdateSigC)
 // and shape control (Eqs. eigdecs .. eigdecrc), all in FP64.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
-  const int sp = blockIdx.x * 256 + threadIdx.x;
-  if (sp >= P.n_sp) return;
-  const SpDesc d = P.sp[sp];
-  if (P.state[d.img].done) return;
-  const ImgDesc I = P.img[d.img];
-  double acc[kStats];
-#pragma unroll
-  for (int j = 0; j < kStats; ++j) acc[j] = 0.0;
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int cx = d.kx - dx, cy = d.ky - dy;
-      if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) continue;
-      const int slot = 3 * (dy + 1) + (dx + 1);
-      // move the spatial moments from the cell origin to the superpixel's
-      // own cell origin: x' = x + ox with ox = (cx - kx) v_x
-      const double ox = (double)(-dx) * I.vx, oy = (double)(-dy) * I.vy;
-      for (int u = 0; u < P.wpc; ++u) {
-        const float* q = reinterpret_cast<const float*>(P.part) +
-                         ((size_t)u * P.n_cell + I.cell_off + cy * I.ncx + cx) * kPartStride +
-                         slot * kStats;
-        const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
-        acc[S_N] += n;
-        acc[S_X] += sx + ox * n;
-        acc[S_Y] += sy + oy * n;
-        acc[S_L] += q[S_L];
-        acc[S_A] += q[S_A];
-        acc[S_B] += q[S_B];
-        acc[S_XX] += q[S_XX] + 2.0 * ox * sx + ox * ox * n;
-        acc[S_XY] += q[S_XY] + ox * sy + oy * sx + ox * oy * n;
-        acc[S_YY] += q[S_YY] + 2.0 * oy * sy + oy * oy * n;
-        acc[S_LL] += q[S_LL];
-        acc[S_AA] += q[S_AA];
-        acc[S_AB] += q[S_AB];
-        acc[S_BB] += q[S_BB];
-      }
-    }
+// The statistics of slot (dx, dy) of the window cell (kx - dx, ky - dy), every
+// wave set of it in order, added to acc with the spatial moments moved from the
+// cell origin to the superpixel's own cell origin: x' = x + ox, ox = (cx - kx) v_x.
+__device__ inline void add_cell_stats(const DevPtrs& P, const ImgDesc& I, int kx, int ky, int dx,
+                                      int dy, double (&acc)[kStats]) {
+  const int cx = kx - dx, cy = ky - dy;
+  if (cx < 0 || cx >= I.ncx || cy < 0 || cy >= I.ncy) return;
+  const int slot = 3 * (dy + 1) + (dx + 1);
+  const double ox = (double)(-dx) * I.vx, oy = (double)(-dy) * I.vy;
+  for (int u = 0; u < P.wpc; ++u) {
+    const float* q = reinterpret_cast<const float*>(P.part) +
+                     ((size_t)u * P.n_cell + I.cell_off + cy * I.ncx + cx) * kPartStride +
+                     slot * kStats;
+    const double n = q[S_N], sx = q[S_X], sy = q[S_Y];
+    acc[S_N] += n;
+    acc[S_X] += sx + ox * n;
+    acc[S_Y] += sy + oy * n;
+    acc[S_L] += q[S_L];
+    acc[S_A] += q[S_A];
+    acc[S_B] += q[S_B];
+    acc[S_XX] += q[S_XX] + 2.0 * ox * sx + ox * ox * n;
+    acc[S_XY] += q[S_XY] + ox * sy + oy * sx + ox * oy * n;
+    acc[S_YY] += q[S_YY] + 2.0 * oy * sy + oy * oy * n;
+    acc[S_LL] += q[S_LL];
+    acc[S_AA] += q[S_AA];
+    acc[S_AB] += q[S_AB];
+    acc[S_BB] += q[S_BB];
   }
-  double* row = P.theta + (size_t)sp * kThetaRow;
+}
+
+// theta^{t+1} of superpixel d from its window statistics: the mean (Eq.
+// UpdateMu), the block covariances about it (Eqs. UpdateSigS, UpdateSigC) and
+// the shape control; false when the mass is below n_min (theta^t is kept).
+// row is the superpixel's FP64 master row (the colour moments were taken
+// about its float32 mean).
+__device__ inline bool theta_from_stats(const double (&acc)[kStats], const SpDesc& d,
+                                        const ImgDesc& I, const double* row, SpTheta& q) {
   const double N = acc[S_N];
-  if (!(N >= I.n_min)) {
-    row[12] = N;  // 0/0 guard: theta_k keeps its value
-    return;
-  }
+  if (!(N >= I.n_min)) return false;
   const double iN = 1.0 / N;
   const double mx = acc[S_X] * iN, my = acc[S_Y] * iN;
   const double mL = acc[S_L] * iN, ma = acc[S_A] * iN, mb = acc[S_B] * iN;
-  SpTheta q;
   q.mx = (double)d.kx * I.vx + mx;
   q.my = (double)d.ky * I.vy + my;
-  // colour moments were taken about the float32 record mean
   q.mL = (double)(float)row[2] + mL;
   q.ma = (double)(float)row[3] + ma;
   q.mb = (double)(float)row[4] + mb;
@@ -630,8 +621,67 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
   q.sxx = s.a; q.sxy = s.b; q.syy = s.c; q.det_s = s.det;
   q.sLL = fmax(acc[S_LL] * iN - mL * mL, I.eps_c);
   q.saa = c.a; q.sab = c.b; q.sbb = c.c; q.det_ab = c.det;
-  store_theta_row(row, q, N);
+  return true;
+}
+
+// One thread per superpixel: the window cells in fixed (dy, dx) order.
+__global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
+  const int sp = blockIdx.x * 256 + threadIdx.x;
+  if (sp >= P.n_sp) return;
+  const SpDesc d = P.sp[sp];
+  if (P.state[d.img].done) return;
+  const ImgDesc I = P.img[d.img];
+  double acc[kStats];
+#pragma unroll
+  for (int j = 0; j < kStats; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) add_cell_stats(P, I, d.kx, d.ky, dx, dy, acc);
+  double* row = P.theta + (size_t)sp * kThetaRow;
+  SpTheta q;
+  if (!theta_from_stats(acc, d, I, row, q)) {
+    row[12] = acc[S_N];  // 0/0 guard: theta_k keeps its value
+    return;
+  }
+  store_theta_row(row, q, acc[S_N]);
   write_records(P, I, d.kx, d.ky, q);
+}
+
+// Sixteen lanes per superpixel, for batches too small to fill the chip with
+// one thread each: lane j < 9 reads window cell j, the sixteen lanes add in a
+// fixed butterfly order, and lane j < 9 writes the record of cell j.  The
+// sums group differently from k_finalize, so the two schedules agree up to
+// FP64 rounding; each is bitwise repeatable.
+constexpr int kGatherLanes = 16;
+
+__global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P) {
+  const int lane = threadIdx.x & (kGatherLanes - 1);
+  const int sp = blockIdx.x * (256 / kGatherLanes) + threadIdx.x / kGatherLanes;
+  if (sp >= P.n_sp) return;  // the whole group of sixteen lanes
+  const SpDesc d = P.sp[sp];
+  if (P.state[d.img].done) return;
+  const ImgDesc I = P.img[d.img];
+  double acc[kStats];
+#pragma unroll
+  for (int j = 0; j < kStats; ++j) acc[j] = 0.0;
+  const int dx = lane % 3 - 1, dy = lane / 3 - 1;
+  if (lane < kSlots) add_cell_stats(P, I, d.kx, d.ky, dx, dy, acc);
+#pragma unroll
+  for (int m = 1; m < kGatherLanes; m <<= 1)
+#pragma unroll
+    for (int j = 0; j < kStats; ++j) acc[j] += __shfl_xor(acc[j], m, kGatherLanes);
+  double* row = P.theta + (size_t)sp * kThetaRow;
+  SpTheta q;
+  const bool ok = theta_from_stats(acc, d, I, row, q);
+  if (!ok) {
+    if (lane == 0) row[12] = acc[S_N];  // 0/0 guard: theta_k keeps its value
+    return;
+  }
+  // every lane has read row[2..4] inside theta_from_stats before lane 0 rewrites it
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) store_theta_row(row, q, acc[S_N]);
+  if (lane < kSlots) write_record_slot(P, I, d.kx, d.ky, q, dx, dy);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,7 +737,11 @@ hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
 
 hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
   if (P.cov_mode) return launch_alt_finalize(P, s);
-  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
+  if (P.glanes == kGatherLanes)
+    hipLaunchKernelGGL(k_finalize_lanes, dim3(blocks_for(P.n_sp, 256 / kGatherLanes)), dim3(256),
+                       0, s, P);
+  else
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 

@@ -184,6 +184,14 @@ class GMMSP:
         check(lib().gmmsp_get_schedule(self.handle, byref(w)))
         return w.value
 
+    def set_gather_lanes(self, lanes_per_superpixel: int):
+        check(lib().gmmsp_set_gather_lanes(self.handle, int(lanes_per_superpixel)))
+
+    def get_gather_lanes(self) -> int:
+        n = c_int32()
+        check(lib().gmmsp_get_gather_lanes(self.handle, byref(n)))
+        return n.value
+
     def set_graph_passes(self, passes: int):
         check(lib().gmmsp_set_graph_passes(self.handle, int(passes)))
 
@@ -191,13 +199,16 @@ class GMMSP:
         dev = torch.cuda.get_device_name(self.device)
         grids = ";".join(f"{W}x{H}/{g.vx}x{g.vy}" for (W, H), g in zip(self.sizes, self.grids))
         import hashlib
-        return f"{dev}|{self.n_images}|" + hashlib.sha256(grids.encode()).hexdigest()[:16]
+        return (f"{dev}|{self.n_images}|m{self.cov_mode}|" +
+                hashlib.sha256(grids.encode()).hexdigest()[:16])
 
     def autotune(self, lab: torch.Tensor, passes: int = 3, cache: str | None = "default") -> int:
-        """Pick the waves-per-cell schedule by timing it on this batch (native
-        loop in the library); results are cached by batch geometry in a JSON
-        file (~/.cache/gmmsp/schedules.json unless another path or None is
-        given).  Leaves the handle initialised by init_seeds."""
+        """Pick the waves-per-cell schedule of the statistics pass, then the
+        lanes per superpixel of the gather, by timing them on this batch
+        (native loops in the library); results are cached by batch geometry in
+        a JSON file (~/.cache/gmmsp/schedules.json unless another path or None
+        is given).  Returns the waves per cell.  Leaves the handle initialised
+        by init_seeds."""
         import json
         import os
         path = None
@@ -215,6 +226,7 @@ class GMMSP:
                 table = {}
         if key in table:
             self.set_schedule(int(table[key]["waves_per_cell"]))
+            self.set_gather_lanes(int(table[key].get("lanes_per_superpixel", 1)))
             self.init_seeds(lab)
             return self.get_schedule()
         ms = np.zeros(3)
@@ -222,8 +234,15 @@ class GMMSP:
         check(lib().gmmsp_autotune(self.handle, self._lab(lab), int(passes),
                                    c_void_p(ms.ctypes.data), byref(w), c_void_p(self._stream())))
         self.tune_ms = dict(zip((1, 2, 4), ms.tolist()))
+        gms = np.zeros(2)
+        lanes = c_int32()
+        check(lib().gmmsp_autotune_gather(self.handle, self._lab(lab), int(passes),
+                                          c_void_p(gms.ctypes.data), byref(lanes),
+                                          c_void_p(self._stream())))
+        self.tune_gather_ms = dict(zip((1, 16), gms.tolist()))
         if path:
-            table[key] = {"waves_per_cell": w.value, "ms": self.tune_ms}
+            table[key] = {"waves_per_cell": w.value, "ms": self.tune_ms,
+                          "lanes_per_superpixel": lanes.value, "gather_ms": self.tune_gather_ms}
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:
                 json.dump(table, f, indent=1)

@@ -5,7 +5,7 @@ nothing here launches a kernel."""
 import ctypes
 import os
 import re
-from ctypes import byref, c_size_t, c_void_p
+from ctypes import byref, c_int32, c_size_t, c_void_p
 
 import numpy as np
 import pytest
@@ -125,6 +125,9 @@ def test_create_rejects_bad_arguments_before_any_device_work():
     assert L.gmmsp_em_iterate(None, None, 1, 0.0, None, None) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_label(None, None, None, None, None) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_init_seeds(None, None, None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_set_gather_lanes(None, 16) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_get_gather_lanes(None, byref(c_int32())) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_autotune_gather(None, None, 1, None, byref(c_int32()), None) == _lib.GMMSP_E_INVAL
 
 
 def test_connectivity_rejects_bad_arguments_before_any_device_work():

@@ -1,6 +1,6 @@
-"""Schedules (waves per cell), the autotuner, graph replay and the 64-image
-uneven batch: every path against the oracle or bitwise against the eager
-single-image path."""
+"""Schedules (waves per cell of the statistics pass, lanes per superpixel of
+the gather), the autotuners, graph replay and the 64-image uneven batch: every
+path against the oracle or bitwise against the eager single-image path."""
 import os
 import sys
 
@@ -35,9 +35,10 @@ def cfg1():
     return im, g, ref
 
 
-def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None):
+def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None, lanes=1):
     m = GMMSP([(im.W, im.H)], K=K or im.K, device=dev)
     m.set_schedule(wpc)
+    m.set_gather_lanes(lanes)
     m.set_graph_passes(graph)
     lab = im.lab.reshape(-1).to(dev)
     m.init_seeds(lab)
@@ -76,6 +77,38 @@ def test_graph_replay_is_bitwise_eager(dev, wpc, graph, tol):
         assert np.array_equal(it, eager["iters"]), rep
 
 
+@pytest.mark.parametrize("wpc", [1, 4])
+def test_gather_lanes_match_one_lane_and_oracle(dev, cfg1, wpc):
+    """16 lanes per superpixel: the FP64 sums group differently from one lane,
+    so theta agrees to FP64 rounding after one pass and to the oracle's
+    tolerances after ten; the schedule is bitwise repeatable and replays
+    bitwise under graph capture."""
+    im, g, ref = cfg1
+    one1 = run(im, dev, 1, wpc)
+    l16_1 = run(im, dev, 1, wpc, lanes=16)
+    np.testing.assert_allclose(l16_1["theta"], one1["theta"], rtol=1e-12, atol=1e-9)
+    a = run(im, dev, 10, wpc, lanes=16)
+    b = run(im, dev, 10, wpc, lanes=16)
+    c = run(im, dev, 10, wpc, graph=4, lanes=16)
+    assert np.array_equal(a["theta"], b["theta"]) and np.array_equal(a["hist"], b["hist"])
+    assert np.array_equal(a["theta"], c["theta"]) and np.array_equal(a["hist"], c["hist"])
+    assert_theta_close(a["theta"], O.theta_to_rows(ref["theta"]), 1e-3, what=f"lanes 16, wpc {wpc}")
+    np.testing.assert_allclose(a["hist"], ref["ll_hist"], rtol=1e-6)
+    assert np.abs(a["R"] - oracle_slots(g, ref["cand"], ref["R"])).max() <= 1e-4
+
+
+def test_gather_lanes_restrictions(dev):
+    im = synth.voronoi_lab(64, 48, 4, 3.0, 5, 12)
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    assert m.get_gather_lanes() == 1
+    with pytest.raises(Exception):
+        m.set_gather_lanes(8)
+    for mode in (1, 2, 3):
+        mm = GMMSP([(im.W, im.H)], K=im.K, device=dev, cov_mode=mode)
+        with pytest.raises(Exception):
+            mm.set_gather_lanes(16)
+
+
 def test_autotune_picks_a_schedule(dev, tmp_path):
     ims = synth.config3_batch(n_images=6)
     lab = synth.pack_batch(ims).to(dev)
@@ -84,12 +117,15 @@ def test_autotune_picks_a_schedule(dev, tmp_path):
     w = m.autotune(lab, passes=2, cache=cache)
     assert w in (1, 2, 4) and m.get_schedule() == w
     assert os.path.exists(cache) and set(m.tune_ms) == {1, 2, 4}
-    say("autotune ms", m.tune_ms, "picked", w)
+    assert set(m.tune_gather_ms) == {1, 16} and m.get_gather_lanes() in (1, 16)
+    say("autotune ms", m.tune_ms, "picked", w, "gather ms", m.tune_gather_ms,
+        "lanes", m.get_gather_lanes())
     # the handle is initialised: EM runs and matches a fresh run with that schedule
     it = m.em_iterate(lab, 3)
     assert list(it) == [3] * 6
     m2 = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
     assert m2.autotune(lab, passes=2, cache=cache) == w          # from the cache
+    assert m2.get_gather_lanes() == m.get_gather_lanes()
     m2.em_iterate(lab, 3)
     assert np.array_equal(m.get_params(), m2.get_params())
 
