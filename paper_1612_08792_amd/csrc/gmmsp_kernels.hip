@@ -221,8 +221,9 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
 // E-step of NP pixels per lane against the nine records of the wave's cell:
 // e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
 // shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
-// Each record value is read once (scalar load) for all NP pixels.
-typedef float f2v __attribute__((ext_vector_type(2)));
+// Each record value is read once (scalar load) for all NP pixels; with NP > 1
+// the offsets come from loff, kOffStride floats per slot in LDS.
+constexpr int kOffStride = 8;
 
 // log2 p(z; theta_k) - cmax2 with the five offsets in vector registers
 __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2, float oL,
@@ -246,7 +247,7 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
                                              const float (&yr)[NP], const float (&L)[NP],
                                              const float (&A)[NP], const float (&B)[NP],
                                              float (&e)[NP][kSlots], float (&sum)[NP],
-                                             float (&shift)[NP]) {
+                                             float (&shift)[NP], const float* loff = nullptr) {
 #pragma unroll
   for (int p = 0; p < NP; ++p) sum[p] = 0.f;
 #pragma unroll
@@ -255,19 +256,14 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
     float l[NP];
     if constexpr (NP > 1) {
       // An FMA reads at most one scalar register, so each offset (the addend
-      // beside a scalar record factor) must sit in a vector register: copy
-      // the offsets once per slot for all NP pixels, two at a time.  (With
-      // one pixel per lane the records are loop invariant and the compiler
-      // keeps the offsets in vector registers by itself.)
-      f2v o12 = *reinterpret_cast<const AS4 f2v*>(f + R_O1);
-      f2v o34 = *reinterpret_cast<const AS4 f2v*>(f + R_O3);
-      float oL = f[R_OL];
-      asm volatile("" : "+v"(o12));
-      asm volatile("" : "+v"(o34));
-      asm volatile("" : "+v"(oL));
+      // beside a scalar record factor) must come from a vector register: the
+      // wave keeps its cell's offsets in LDS and reads them by broadcast, which
+      // costs no vector ALU issue and no scalar registers.
+      const float4 o = *reinterpret_cast<const float4*>(loff + s * kOffStride);
+      const float oL = loff[s * kOffStride + 4];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
-        l[p] = eval_l_o(f, o12.x, o12.y, oL, o34.x, o34.y, xr[p], yr[p], L[p], A[p], B[p]);
+        l[p] = eval_l_o(f, o.x, o.y, oL, o.z, o.w, xr[p], yr[p], L[p], A[p], B[p]);
     } else {
 #pragma unroll
       for (int p = 0; p < NP; ++p) l[p] = eval_l(f, xr[p], yr[p], L[p], A[p], B[p]);
@@ -425,6 +421,19 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     const int step = 128 * wpc;
     const int dr = step / w, dc = step - (step / w) * w;
     const int n_pair = npix > 64 ? (npix - 64 + 127) >> 7 : 0;  // rounds with base + 64 < npix
+    // the nine slots' offsets (O1, O2, O3, O4, OL) in this wave's own LDS
+    // block, written by lanes 0..8 and read back by every lane
+    __shared__ float s_off[kWavesPerBlock * kSlots * kOffStride];
+    float* woff = s_off + (threadIdx.x >> 6) * (kSlots * kOffStride);
+    if (lane < kSlots) {
+      const float* g = P.rec + (size_t)cell * (kSlots * kRecFloats) + lane * kRecFloats;
+      *reinterpret_cast<float4*>(woff + lane * kOffStride) =
+          make_float4(g[R_O1], g[R_O2], g[R_O3], g[R_O4]);
+      woff[lane * kOffStride + 4] = g[R_OL];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int rd = sub; rd < n_pair; rd += wpc) {
       const int base = rd << 7;
       // The 144 record floats do not fit the scalar registers; an opaque zero
@@ -440,7 +449,11 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
       const float xr[2] = {(float)c1, (float)c2}, yr[2] = {(float)r1, (float)r2};
       float e[2][kSlots], sum[2], shift[2];
-      estep_pixels<2>(rec, xr, yr, L, A, B, e, sum, shift);
+      // likewise an opaque zero keeps the LDS offsets from being hoisted into
+      // 45 vector registers
+      int vz = 0;
+      asm volatile("" : "+v"(vz));
+      estep_pixels<2>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
       const float inv[2] = {__builtin_amdgcn_rcpf(sum[0]), v2 ? __builtin_amdgcn_rcpf(sum[1]) : 0.f};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;
