@@ -211,13 +211,16 @@ __global__ __launch_bounds__(256) void k3_set_params(DevPtrs P, const double* __
   write_records3(P, I, d.kx, d.ky, q);
 }
 
-__device__ __forceinline__ float eval3(const AS4 float* f, float xr, float yr, float L, float A,
-                                       float B) {
-  const float t1 = fmaf(f[Q_L11], xr, fmaf(f[Q_L12], yr, f[Q_O1]));
-  const float t2 = fmaf(f[Q_L22], yr, f[Q_O2]);
-  const float u1 = fmaf(f[Q_U11], L, fmaf(f[Q_U12], A, fmaf(f[Q_U13], B, f[Q_P1])));
-  const float u2 = fmaf(f[Q_U22], A, fmaf(f[Q_U23], B, f[Q_P2]));
-  const float u3 = fmaf(f[Q_U33], B, f[Q_P3]);
+// the offsets of t1, t2, u1, u2, u3, read from the wave's LDS block
+constexpr int kOffIdx3[5] = {Q_O1, Q_O2, Q_P1, Q_P2, Q_P3};
+
+__device__ __forceinline__ float eval3(const AS4 float* f, const float (&o)[5], float xr, float yr,
+                                       float L, float A, float B) {
+  const float t1 = fmaf(f[Q_L11], xr, fmaf(f[Q_L12], yr, o[0]));
+  const float t2 = fmaf(f[Q_L22], yr, o[1]);
+  const float u1 = fmaf(f[Q_U11], L, fmaf(f[Q_U12], A, fmaf(f[Q_U13], B, o[2])));
+  const float u2 = fmaf(f[Q_U22], A, fmaf(f[Q_U23], B, o[3]));
+  const float u3 = fmaf(f[Q_U33], B, o[4]);
   float l = fmaf(-t1, t1, f[Q_C]);
   l = fmaf(-t2, t2, l);
   l = fmaf(-u1, u1, l);
@@ -229,7 +232,7 @@ __device__ __forceinline__ float eval3(const AS4 float* f, float xr, float yr, f
 enum CellMode3 { C3_STATS = 0, C3_LABEL = 1, C3_EXPORT_R = 2, C3_EXPORT_CAND = 3 };
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k3_cells(DevPtrs P, const float* __restrict__ lab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k3_cells(DevPtrs P, const float* __restrict__ lab,
                                                 int32_t* __restrict__ out_i,
                                                 float* __restrict__ out_f) {
   const int lane = threadIdx.x & 63;
@@ -271,12 +274,17 @@ __global__ __launch_bounds__(256) void k3_cells(DevPtrs P, const float* __restri
     for (int i = 0; i < NS + 1; ++i) acc[i] = 0.f;
   }
   float llacc = 0.f;
+  __shared__ float s_off[kWavesPerBlock * kOffBlock];
+  float* woff0 = s_off + (threadIdx.x >> 6) * kOffBlock;
+  stage_offsets(woff0, P.rec + (size_t)cell * (kSlots * kRec3), kRec3, kOffIdx3, lane);
   for (int p = lane; p < npix; p += 64) {
-    // an opaque zero offset: the records are re-read each round by scalar
-    // loads rather than held in (too few) scalar registers
-    int zero = 0;
+    // opaque zero offsets: the records are re-read each round by scalar loads
+    // and the offsets by LDS reads, rather than held in (too few) registers
+    int zero = 0, vz = 0;
     asm volatile("" : "+s"(zero));
+    asm volatile("" : "+v"(vz));
     const AS4 float* rec = rec0 + zero;
+    const float* woff = woff0 + vz;
     const int row = p / w, col = p - row * w;
     const float* px = img + 3 * (row * W + col);
     const float L = px[0], A = px[1], B = px[2];
@@ -285,7 +293,9 @@ __global__ __launch_bounds__(256) void k3_cells(DevPtrs P, const float* __restri
     float sum = 0.f;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-      e[s] = __builtin_amdgcn_exp2f(eval3(rec + s * kRec3, xr, yr, L, A, B));
+      float o[5];
+      load_offsets(woff, s, o);
+      e[s] = __builtin_amdgcn_exp2f(eval3(rec + s * kRec3, o, xr, yr, L, A, B));
       sum += e[s];
     }
     float shift = 0.f;
@@ -295,7 +305,9 @@ __global__ __launch_bounds__(256) void k3_cells(DevPtrs P, const float* __restri
       float m = -INFINITY;
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) {
-        lv[s] = eval3(rec + s * kRec3, xr, yr, L, A, B);
+        float o[5];
+        load_offsets(woff, s, o);
+        lv[s] = eval3(rec + s * kRec3, o, xr, yr, L, A, B);
         m = fmaxf(m, lv[s]);
       }
       sum = 0.f;

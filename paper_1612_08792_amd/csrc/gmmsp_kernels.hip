@@ -222,8 +222,7 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
 // e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
 // shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
 // Each record value is read once (scalar load) for all NP pixels; with NP > 1
-// the offsets come from loff, kOffStride floats per slot in LDS.
-constexpr int kOffStride = 8;
+// the offsets (O1, O2, O3, O4, OL) come from the wave's LDS block loff.
 
 // log2 p(z; theta_k) - cmax2 with the five offsets in vector registers
 __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2, float oL,
@@ -255,15 +254,11 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
     const AS4 float* f = rec + s * kRecFloats;
     float l[NP];
     if constexpr (NP > 1) {
-      // An FMA reads at most one scalar register, so each offset (the addend
-      // beside a scalar record factor) must come from a vector register: the
-      // wave keeps its cell's offsets in LDS and reads them by broadcast, which
-      // costs no vector ALU issue and no scalar registers.
-      const float4 o = *reinterpret_cast<const float4*>(loff + s * kOffStride);
-      const float oL = loff[s * kOffStride + 4];
+      float o[5];
+      load_offsets(loff, s, o);
 #pragma unroll
       for (int p = 0; p < NP; ++p)
-        l[p] = eval_l_o(f, o.x, o.y, oL, o.z, o.w, xr[p], yr[p], L[p], A[p], B[p]);
+        l[p] = eval_l_o(f, o[0], o[1], o[4], o[2], o[3], xr[p], yr[p], L[p], A[p], B[p]);
     } else {
 #pragma unroll
       for (int p = 0; p < NP; ++p) l[p] = eval_l(f, xr[p], yr[p], L[p], A[p], B[p]);
@@ -421,19 +416,11 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     const int step = 128 * wpc;
     const int dr = step / w, dc = step - (step / w) * w;
     const int n_pair = npix > 64 ? (npix - 64 + 127) >> 7 : 0;  // rounds with base + 64 < npix
-    // the nine slots' offsets (O1, O2, O3, O4, OL) in this wave's own LDS
-    // block, written by lanes 0..8 and read back by every lane
-    __shared__ float s_off[kWavesPerBlock * kSlots * kOffStride];
-    float* woff = s_off + (threadIdx.x >> 6) * (kSlots * kOffStride);
-    if (lane < kSlots) {
-      const float* g = P.rec + (size_t)cell * (kSlots * kRecFloats) + lane * kRecFloats;
-      *reinterpret_cast<float4*>(woff + lane * kOffStride) =
-          make_float4(g[R_O1], g[R_O2], g[R_O3], g[R_O4]);
-      woff[lane * kOffStride + 4] = g[R_OL];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // the nine slots' offsets in this wave's own LDS block
+    __shared__ float s_off[kWavesPerBlock * kOffBlock];
+    float* woff = s_off + (threadIdx.x >> 6) * kOffBlock;
+    constexpr int kOffIdx[5] = {R_O1, R_O2, R_O3, R_O4, R_OL};
+    stage_offsets(woff, P.rec + (size_t)cell * (kSlots * kRecFloats), kRecFloats, kOffIdx, lane);
     for (int rd = sub; rd < n_pair; rd += wpc) {
       const int base = rd << 7;
       // The 144 record floats do not fit the scalar registers; an opaque zero

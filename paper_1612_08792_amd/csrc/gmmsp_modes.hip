@@ -286,13 +286,15 @@ __device__ inline SpGray clamp_gray(double mx, double my, double mI, double sxx,
 
 struct FullModel {
   static constexpr int kRec = kRecF, kStat = kStatsF, kPart = kPartF, kCh = 3, kC = F_C;
-  static __device__ __forceinline__ float eval(const AS4 float* f, float xr, float yr,
-                                               const float (&c)[kCh]) {
+  static constexpr int kNOff = 5;  // the offsets of the five whitened coordinates
+  static constexpr int kOffIdx[kNOff] = {F_O, F_O + 1, F_O + 2, F_O + 3, F_O + 4};
+  static __device__ __forceinline__ float eval(const AS4 float* f, const float (&o)[kNOff],
+                                               float xr, float yr, const float (&c)[kCh]) {
     const float z[5] = {xr, yr, c[0], c[1], c[2]};
     float l = f[F_C];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-      float u = f[F_O + i];
+      float u = o[i];
 #pragma unroll
       for (int j = i; j < 5; ++j) u = fmaf(f[F_U + ut(i, j)], z[j], u);
       l = fmaf(-u, u, l);
@@ -330,11 +332,13 @@ struct FullModel {
 
 struct GrayModel {
   static constexpr int kRec = kRecG, kStat = kStatsG, kPart = kPartG, kCh = 1, kC = H_C;
-  static __device__ __forceinline__ float eval(const AS4 float* f, float xr, float yr,
-                                               const float (&c)[kCh]) {
-    const float t1 = fmaf(f[H_L11], xr, fmaf(f[H_L12], yr, f[H_O1]));
-    const float t2 = fmaf(f[H_L22], yr, f[H_O2]);
-    const float w = fmaf(f[H_UI], c[0], f[H_PI]);
+  static constexpr int kNOff = 3;  // the offsets of t1, t2 and w
+  static constexpr int kOffIdx[kNOff] = {H_O1, H_O2, H_PI};
+  static __device__ __forceinline__ float eval(const AS4 float* f, const float (&o)[kNOff],
+                                               float xr, float yr, const float (&c)[kCh]) {
+    const float t1 = fmaf(f[H_L11], xr, fmaf(f[H_L12], yr, o[0]));
+    const float t2 = fmaf(f[H_L22], yr, o[1]);
+    const float w = fmaf(f[H_UI], c[0], o[2]);
     float l = fmaf(-t1, t1, f[H_C]);
     l = fmaf(-t2, t2, l);
     return fmaf(-w, w, l);
@@ -366,7 +370,8 @@ __global__ __launch_bounds__(256) void km_clear_records(float* rec, size_t n_rec
   d[M::kC] = -INFINITY;
 }
 
-// One wave per cell, one pixel per lane per round of 64.
+// One wave per cell, one pixel per lane per round of 64; the record offsets
+// are read from the wave's LDS block.
 template <class M, int MODE>
 __global__ __launch_bounds__(256) void km_cells(DevPtrs P, const float* __restrict__ in,
                                                 int32_t* __restrict__ out_i,
@@ -412,12 +417,17 @@ __global__ __launch_bounds__(256) void km_cells(DevPtrs P, const float* __restri
   }
   float llacc = 0.f;
   const float* img = in + (size_t)kCh * pix0;
+  __shared__ float s_off[kWavesPerBlock * kOffBlock];
+  float* woff0 = s_off + (threadIdx.x >> 6) * kOffBlock;
+  stage_offsets(woff0, P.rec + (size_t)cell * (kSlots * kRec), kRec, M::kOffIdx, lane);
   for (int p = lane; p < npix; p += 64) {
-    // an opaque zero offset: the records are re-read each round by scalar
-    // loads rather than held in scalar registers
-    int zero = 0;
+    // opaque zero offsets: the records are re-read each round by scalar loads
+    // and the offsets by LDS reads, rather than held in registers
+    int zero = 0, vz = 0;
     asm volatile("" : "+s"(zero));
+    asm volatile("" : "+v"(vz));
     const AS4 float* rec = rec0 + zero;
+    const float* woff = woff0 + vz;
     const int row = p / w, col = p - row * w;
     const float* px = img + (size_t)kCh * ((int64_t)row * W + col);
     float c[kCh];
@@ -428,7 +438,9 @@ __global__ __launch_bounds__(256) void km_cells(DevPtrs P, const float* __restri
     float sum = 0.f;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-      e[s] = __builtin_amdgcn_exp2f(M::eval(rec + s * kRec, xr, yr, c));
+      float o[M::kNOff];
+      load_offsets(woff, s, o);
+      e[s] = __builtin_amdgcn_exp2f(M::eval(rec + s * kRec, o, xr, yr, c));
       sum += e[s];
     }
     float shift = 0.f;
@@ -438,7 +450,9 @@ __global__ __launch_bounds__(256) void km_cells(DevPtrs P, const float* __restri
       float m = -INFINITY;
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) {
-        lv[s] = M::eval(rec + s * kRec, xr, yr, c);
+        float o[M::kNOff];
+        load_offsets(woff, s, o);
+        lv[s] = M::eval(rec + s * kRec, o, xr, yr, c);
         m = fmaxf(m, lv[s]);
       }
       sum = 0.f;

@@ -89,4 +89,43 @@ __device__ __forceinline__ void wave_reduce_scatter(float (&v)[CAP], int lane) {
   bfly_dpp<N5, 0, 0xB1>(v, lane);   // quad_perm [1,0,3,2], partner lane ^ 1
 }
 
+// ---------------------------------------------------------------------------
+// Record offsets through LDS.  A VALU FMA reads at most one scalar register, so
+// the offset of a whitening FMA (the addend beside a scalar record factor) has
+// to come from a vector register.  The per-cell kernels keep the nine slots'
+// offsets (at most 5 per record) in the wave's own block of LDS, kOffStride
+// floats per slot, and read them back by broadcast each round: LDS reads issue
+// on their own port, so this costs no VALU issue and no scalar registers.
+// ---------------------------------------------------------------------------
+constexpr int kOffStride = 8;
+constexpr int kOffBlock = 9 * kOffStride;  // floats per wave
+
+// lanes 0..8 copy the offsets idx[0..N) of their slot's record (rec_cell: the
+// cell's nine records, rec_floats each); every lane of the wave may read the
+// block after the call.  Only the calling wave touches its block, so a wave
+// barrier orders the writes before the reads.
+template <int N>
+__device__ __forceinline__ void stage_offsets(float* woff, const float* rec_cell, int rec_floats,
+                                              const int (&idx)[N], int lane) {
+  static_assert(N <= 5, "at most five offsets per record");
+  if (lane < 9) {
+    const float* g = rec_cell + lane * rec_floats;
+#pragma unroll
+    for (int i = 0; i < N; ++i) woff[lane * kOffStride + i] = g[idx[i]];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// the offsets of slot s: four by one 16-byte read, the fifth by one more
+template <int N>
+__device__ __forceinline__ void load_offsets(const float* woff, int s, float (&o)[N]) {
+  const float4 q = *reinterpret_cast<const float4*>(woff + s * kOffStride);
+  const float v[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int i = 0; i < N && i < 4; ++i) o[i] = v[i];
+  if constexpr (N > 4) o[4] = woff[s * kOffStride + 4];
+}
+
 }  // namespace gmmsp
