@@ -98,17 +98,17 @@ __device__ __forceinline__ void wave_reduce_scatter(float (&v)[CAP], int lane) {
 // on their own port, so this costs no VALU issue and no scalar registers.
 // ---------------------------------------------------------------------------
 constexpr int kOffStride = 8;
-constexpr int kOffBlock = 9 * kOffStride;  // floats per wave
+constexpr int kOffBlock = kSlots * kOffStride;  // floats per wave
 
-// lanes 0..8 copy the offsets idx[0..N) of their slot's record (rec_cell: the
-// cell's nine records, rec_floats each); every lane of the wave may read the
+// lanes 0..kSlots-1 copy the offsets idx[0..N) of their slot's record (rec_cell:
+// the cell's nine records, rec_floats each); every lane of the wave may read the
 // block after the call.  Only the calling wave touches its block, so a wave
 // barrier orders the writes before the reads.
 template <int N>
 __device__ __forceinline__ void stage_offsets(float* woff, const float* rec_cell, int rec_floats,
                                               const int (&idx)[N], int lane) {
   static_assert(N <= 5, "at most five offsets per record");
-  if (lane < 9) {
+  if (lane < kSlots) {
     const float* g = rec_cell + lane * rec_floats;
 #pragma unroll
     for (int i = 0; i < N; ++i) woff[lane * kOffStride + i] = g[idx[i]];
