@@ -221,8 +221,9 @@ __device__ __forceinline__ float eval_l(const AS4 float* f, float xr, float yr, 
 // E-step of NP pixels per lane against the nine records of the wave's cell:
 // e[p][s] is proportional to R_(i_p, s) (Eq. Rik), sum[p] = sum_s e[p][s], and
 // shift[p] is the log2 offset of e (0 unless all nine densities underflowed).
-// Each record value is read once (scalar load) for all NP pixels; with NP > 1
-// the offsets (O1, O2, O3, O4, OL) come from the wave's LDS block loff.
+// Each record value is read once (scalar load) for all NP pixels; with kLdsOff
+// the offsets (O1, O2, O3, O4, OL) come from the wave's LDS block loff (the
+// statistics pass), otherwise from the records.
 
 // log2 p(z; theta_k) - cmax2 with the five offsets in vector registers
 __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2, float oL,
@@ -241,7 +242,7 @@ __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2
   return l;
 }
 
-template <int NP>
+template <int NP, bool kLdsOff = false>
 __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (&xr)[NP],
                                              const float (&yr)[NP], const float (&L)[NP],
                                              const float (&A)[NP], const float (&B)[NP],
@@ -253,7 +254,7 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
   for (int s = 0; s < kSlots; ++s) {
     const AS4 float* f = rec + s * kRecFloats;
     float l[NP];
-    if constexpr (NP > 1) {
+    if constexpr (kLdsOff) {
       float o[5];
       load_offsets(loff, s, o);
 #pragma unroll
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       // 45 vector registers
       int vz = 0;
       asm volatile("" : "+v"(vz));
-      estep_pixels<2>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
+      estep_pixels<2, true>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
       const float inv[2] = {__builtin_amdgcn_rcpf(sum[0]), v2 ? __builtin_amdgcn_rcpf(sum[1]) : 0.f};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const float xr[1] = {(float)c1}, yr[1] = {(float)r1};
       const float L[1] = {q1[0]}, A[1] = {q1[1]}, B[1] = {q1[2]};
       float e[1][kSlots], sum[1], shift[1];
-      estep_pixels<1>(rec, xr, yr, L, A, B, e, sum, shift);
+      estep_pixels<1, true>(rec, xr, yr, L, A, B, e, sum, shift, woff);
       const float inv[1] = {__builtin_amdgcn_rcpf(sum[0])};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       accumulate_stats<1>(rec, acc, e, inv, xr, yr, L, A, B);
