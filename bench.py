@@ -208,6 +208,11 @@ def main():
     m = GMMSP(sizes, K=K_req, device=dev)
     labels = torch.empty(m.n_pixels, dtype=torch.int32, device=dev)
     n_pix = m.n_pixels
+    # schedules (waves per cell, lanes per superpixel of the gather) timed on
+    # this batch by the library's autotuners, outside the timed region
+    wpc = m.autotune(lab, passes=3, cache=None)
+    log(f"autotuned: {wpc} waves per cell, {m.get_gather_lanes()} gather lanes "
+        f"(E-step ms {m.tune_ms}, gather ms {m.tune_gather_ms})")
     params = None
     if args.mode in ("both", "warm"):
         params = load_or_train_weights(dev)
@@ -308,6 +313,7 @@ def main():
             "passes_max": int(iters.max()),
             "estep_mpix_per_s_per_pass": round(per_iter_mpix, 1),
             "plain_vs_warm": compare,
+            "schedule": {"waves_per_cell": m.get_schedule(), "gather_lanes": m.get_gather_lanes()},
         },
         "roofline": {
             "bound": "alu",

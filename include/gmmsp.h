@@ -197,20 +197,23 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
 
 /* Schedule of the per-superpixel gather of the M-step (Eqs. UpdateMu,
  * UpdateSigS, UpdateSigC and the shape control): 1 lane per superpixel
- * (default; the window cells are added in a fixed sequential order) or 16
- * lanes per superpixel (one window cell per lane, added in a fixed butterfly
- * order, then one record per lane), for batches too small to fill the chip.
- * The two group the FP64 sums differently; each is bitwise repeatable.  With
- * cov_mode 1, 2 or 3 only 1 is accepted (E_INVAL otherwise). */
+ * (default; the window cells are added in a fixed sequential order), or G = 4
+ * or 16 lanes per superpixel (lane j adds window cells j, j + G, ... in that
+ * order, the G lanes add in a fixed butterfly order, and lane j writes the
+ * records of the same cells), for batches that one lane per superpixel leaves
+ * short of waves.  The schedules group the FP64 sums differently; each is
+ * bitwise repeatable.  With cov_mode 1, 2 or 3 only 1 is accepted (E_INVAL
+ * otherwise). */
 int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel);
 int gmmsp_get_gather_lanes(const gmmsp_handle* h, int32_t* lanes_per_superpixel);
 
-/* Autotuner of the gather: for 1 and 16 lanes per superpixel, one statistics
- * pass from the grid initialisation, then `passes` gathers (after one untimed)
- * timed with HIP events on `stream`; keeps the faster (ties to 1) and leaves
- * the handle initialised by gmmsp_init_seeds.  Run it after gmmsp_autotune
- * (it gathers the statistics of the chosen waves per cell).  ms_host
- * (nullable, 2 doubles): the measured times (-1 for a schedule not timed). */
+/* Autotuner of the gather: for 1, 4 and 16 lanes per superpixel, one
+ * statistics pass from the grid initialisation, then `passes` gathers (after
+ * one untimed) timed with HIP events on `stream`; keeps the fastest (ties to
+ * the fewer lanes) and leaves the handle initialised by gmmsp_init_seeds.  Run
+ * it after gmmsp_autotune (it gathers the statistics of the chosen waves per
+ * cell).  ms_host (nullable, 3 doubles, in the order 1, 4, 16): the measured
+ * times (-1 for a schedule not timed). */
 int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
                           double* ms_host, int32_t* chosen, void* stream);
 

@@ -112,7 +112,9 @@ def main():
         est = p["estep_ms"] / p["launches"]
         tflops = p["pair_evals"] * FLOPS_PER_PAIR / (p["estep_ms"] / 1e3) / 1e12
         r = dict(config=c, workload=name, images=len(ims), pixels=m.n_pixels, T=T,
-                 waves_per_cell=wpc, gather_lanes=m.get_gather_lanes(), mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
+                 waves_per_cell=wpc, gather_lanes=m.get_gather_lanes(),
+                 gather_ms={k: round(v, 4) for k, v in m.tune_gather_ms.items()},
+                 mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
                  ms_per_iteration=round(1e3 * t / T, 4), estep_ms_per_launch=round(est, 4),
                  estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
                  pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),

@@ -615,8 +615,8 @@ int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell) {
 
 int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
-  if (lanes_per_superpixel != 1 && lanes_per_superpixel != 16)
-    return fail(GMMSP_E_INVAL, "lanes per superpixel must be 1 or 16");
+  if (lanes_per_superpixel != 1 && lanes_per_superpixel != 4 && lanes_per_superpixel != 16)
+    return fail(GMMSP_E_INVAL, "lanes per superpixel must be 1, 4 or 16");
   if (h->P.cov_mode != 0 && lanes_per_superpixel != 1)
     return fail(GMMSP_E_INVAL, "cov_mode %d gathers with one lane per superpixel", h->P.cov_mode);
   h->P.glanes = lanes_per_superpixel;
@@ -690,10 +690,10 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
   if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
-  const int32_t cand[2] = {1, 16};
-  const int n_cand = h->P.cov_mode != 0 ? 1 : 2;
+  const int32_t cand[3] = {1, 4, 16};
+  const int n_cand = h->P.cov_mode != 0 ? 1 : 3;
   if (ms_host)
-    for (int c = 0; c < 2; ++c) ms_host[c] = -1.0;
+    for (int c = 0; c < 3; ++c) ms_host[c] = -1.0;
   double best = 0.0;
   int32_t pick = 1;
   hipEvent_t a = nullptr, b = nullptr;

@@ -106,7 +106,7 @@ struct DevPtrs {
   int32_t* n_done;          // images that have stopped
   int32_t n_img, n_cell, n_sp;
   int32_t wpc;              // waves per cell of the statistics pass (1, 2 or 4)
-  int32_t glanes;           // lanes per superpixel of the gather (1 or 16)
+  int32_t glanes;           // lanes per superpixel of the gather (1, 4 or 16)
   int32_t cov_mode;         // 0 split colour blocks; 1 3x3 colour block (gmmsp_cov3.hip);
                             // 2 full 5x5, 3 grayscale (gmmsp_modes.hip)
 };

@@ -649,29 +649,29 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
   write_records(P, I, d.kx, d.ky, q);
 }
 
-// Sixteen lanes per superpixel, for batches too small to fill the chip with
-// one thread each: lane j < 9 reads window cell j, the sixteen lanes add in a
-// fixed butterfly order, and lane j < 9 writes the record of cell j.  The
-// sums group differently from k_finalize, so the two schedules agree up to
-// FP64 rounding; each is bitwise repeatable.
-constexpr int kGatherLanes = 16;
-
+// G lanes per superpixel (G = 4 or 16), for batches that one thread per
+// superpixel leaves short of waves: lane j reads window cells j, j + G, ... in
+// that order, the G lanes add in a fixed butterfly order, every lane forms
+// theta, and lane j writes the records of cells j, j + G, ...  The sums group
+// differently from k_finalize, so the schedules agree up to FP64 rounding;
+// each is bitwise repeatable.
+template <int G>
 __global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P) {
-  const int lane = threadIdx.x & (kGatherLanes - 1);
-  const int sp = blockIdx.x * (256 / kGatherLanes) + threadIdx.x / kGatherLanes;
-  if (sp >= P.n_sp) return;  // the whole group of sixteen lanes
+  static_assert(G == 4 || G == 16, "4 or 16 lanes per superpixel");
+  const int lane = threadIdx.x & (G - 1);
+  const int sp = blockIdx.x * (256 / G) + threadIdx.x / G;
+  if (sp >= P.n_sp) return;  // the whole group of G lanes
   const SpDesc d = P.sp[sp];
   if (P.state[d.img].done) return;
   const ImgDesc I = P.img[d.img];
   double acc[kStats];
 #pragma unroll
   for (int j = 0; j < kStats; ++j) acc[j] = 0.0;
-  const int dx = lane % 3 - 1, dy = lane / 3 - 1;
-  if (lane < kSlots) add_cell_stats(P, I, d.kx, d.ky, dx, dy, acc);
+  for (int c = lane; c < kSlots; c += G) add_cell_stats(P, I, d.kx, d.ky, c % 3 - 1, c / 3 - 1, acc);
 #pragma unroll
-  for (int m = 1; m < kGatherLanes; m <<= 1)
+  for (int m = 1; m < G; m <<= 1)
 #pragma unroll
-    for (int j = 0; j < kStats; ++j) acc[j] += __shfl_xor(acc[j], m, kGatherLanes);
+    for (int j = 0; j < kStats; ++j) acc[j] += __shfl_xor(acc[j], m, G);
   double* row = P.theta + (size_t)sp * kThetaRow;
   SpTheta q;
   const bool ok = theta_from_stats(acc, d, I, row, q);
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P) {
   // every lane has read row[2..4] inside theta_from_stats before lane 0 rewrites it
   __builtin_amdgcn_wave_barrier();
   if (lane == 0) store_theta_row(row, q, acc[S_N]);
-  if (lane < kSlots) write_record_slot(P, I, d.kx, d.ky, q, dx, dy);
+  for (int c = lane; c < kSlots; c += G) write_record_slot(P, I, d.kx, d.ky, q, c % 3 - 1, c / 3 - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,9 +738,10 @@ hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
 
 hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
   if (P.cov_mode) return launch_alt_finalize(P, s);
-  if (P.glanes == kGatherLanes)
-    hipLaunchKernelGGL(k_finalize_lanes, dim3(blocks_for(P.n_sp, 256 / kGatherLanes)), dim3(256),
-                       0, s, P);
+  if (P.glanes == 16)
+    hipLaunchKernelGGL(k_finalize_lanes<16>, dim3(blocks_for(P.n_sp, 256 / 16)), dim3(256), 0, s, P);
+  else if (P.glanes == 4)
+    hipLaunchKernelGGL(k_finalize_lanes<4>, dim3(blocks_for(P.n_sp, 256 / 4)), dim3(256), 0, s, P);
   else
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
   return hipGetLastError();

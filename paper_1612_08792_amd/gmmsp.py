@@ -234,12 +234,12 @@ class GMMSP:
         check(lib().gmmsp_autotune(self.handle, self._lab(lab), int(passes),
                                    c_void_p(ms.ctypes.data), byref(w), c_void_p(self._stream())))
         self.tune_ms = dict(zip((1, 2, 4), ms.tolist()))
-        gms = np.zeros(2)
+        gms = np.zeros(3)
         lanes = c_int32()
         check(lib().gmmsp_autotune_gather(self.handle, self._lab(lab), int(passes),
                                           c_void_p(gms.ctypes.data), byref(lanes),
                                           c_void_p(self._stream())))
-        self.tune_gather_ms = dict(zip((1, 16), gms.tolist()))
+        self.tune_gather_ms = dict(zip((1, 4, 16), gms.tolist()))
         if path:
             table[key] = {"waves_per_cell": w.value, "ms": self.tune_ms,
                           "lanes_per_superpixel": lanes.value, "gather_ms": self.tune_gather_ms}
