@@ -187,10 +187,11 @@ int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream);
 int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell);
 int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
 
-/* Autotuner: times `passes` statistics passes (after one untimed pass) from the
- * grid initialisation for each schedule 1, 2, 4 with HIP events on `stream`,
- * keeps the fastest (ties to fewer waves), and leaves the handle initialised
- * by gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times (-1
+/* Autotuner: times `passes` statistics passes (after three untimed passes)
+ * from the grid initialisation for each schedule 1, 2, 4 with HIP events on
+ * `stream`; a schedule with more waves is kept only if it is more than 3 %
+ * faster than the best with fewer.  Leaves the handle initialised by
+ * gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times (-1
  * for a schedule not timed; with cov_mode 1, 2 or 3 only schedule 1 is). */
 int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
                    int32_t* chosen, void* stream);
@@ -209,8 +210,9 @@ int gmmsp_get_gather_lanes(const gmmsp_handle* h, int32_t* lanes_per_superpixel)
 
 /* Autotuner of the gather: for 1, 4 and 16 lanes per superpixel, one
  * statistics pass from the grid initialisation, then `passes` gathers (after
- * one untimed) timed with HIP events on `stream`; keeps the fastest (ties to
- * the fewer lanes) and leaves the handle initialised by gmmsp_init_seeds.  Run
+ * one untimed) timed with HIP events on `stream`; more lanes are kept only if
+ * more than 3 % faster than the best with fewer.  Leaves the handle
+ * initialised by gmmsp_init_seeds.  Run
  * it after gmmsp_autotune (it gathers the statistics of the chosen waves per
  * cell).  ms_host (nullable, 3 doubles, in the order 1, 4, 16): the measured
  * times (-1 for a schedule not timed). */

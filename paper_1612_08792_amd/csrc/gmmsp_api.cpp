@@ -636,6 +636,12 @@ int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes) {
   return GMMSP_OK;
 }
 
+// Both autotuners try their candidates from the smallest up and move to a
+// larger one only when it beats the best so far by more than 3 %, so that
+// timing noise does not pick a schedule that is no faster.
+constexpr double kTuneMargin = 0.97;
+constexpr int32_t kTuneWarm = 3;  // untimed passes before the timed ones
+
 int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
                    int32_t* chosen, void* stream) {
   if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
@@ -655,8 +661,9 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
     e = launch_reset_state(h->P, s);
     if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
     double tot = 0.0;
-    // one untimed pass, then `passes` timed ones
-    for (int32_t i = 0; i <= passes && e == hipSuccess; ++i) {
+    // kTuneWarm untimed passes (the first passes from the grid seeds run
+    // slower than later ones), then `passes` timed ones
+    for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
       e = hipEventRecord(a, s);
       if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
       if (e == hipSuccess) e = hipEventRecord(b, s);
@@ -665,10 +672,10 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      if (i > 0) tot += ms;
+      if (i >= kTuneWarm) tot += ms;
     }
     if (ms_host) ms_host[c] = tot;
-    if (c == 0 || tot < best) {
+    if (c == 0 || tot < kTuneMargin * best) {
       best = tot;
       pick = cand[c];
     }
@@ -716,7 +723,7 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
       if (i > 0) tot += ms;  // the first launch is untimed
     }
     if (ms_host) ms_host[c] = tot;
-    if (c == 0 || tot < best) {
+    if (c == 0 || tot < kTuneMargin * best) {
       best = tot;
       pick = cand[c];
     }
