@@ -229,11 +229,15 @@ def test_far_outlier_pixel_uses_shifted_softmax(dev):
 # ---------------------------------------------------------------------------
 # full-size 4K image: sampled one-step parity in the launch shape of the bench
 # ---------------------------------------------------------------------------
-def test_4k_sampled_one_step(dev):
-    say("4K sampled one-step parity")
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_4k_sampled_one_step(dev, lanes):
+    """Both gathers the 4K batch uses: one lane per superpixel (default) and
+    four (the autotuned choice the benchmark times)."""
+    say(f"4K sampled one-step parity, {lanes} gather lanes")
     im = synth.config5_batch(device=dev, n_images=1)[0]
     g = O.make_grid(im.W, im.H, K=im.K)
     m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    m.set_gather_lanes(lanes)
     lab = im.lab.reshape(-1).contiguous()
     m.init_seeds(lab)
     m.em_iterate(lab, 3)
@@ -268,7 +272,7 @@ def test_4k_sampled_one_step(dev):
                                   theta3.sigma[k], O.Params())
         want4[j] = O.theta_to_rows(O.Theta(mu[None], sig[None], np.array([Nk])))[0]
         rows4[j] = th4[k]
-    e = assert_theta_close(rows4, want4, 1e-5, what="4K one step")
+    e = assert_theta_close(rows4, want4, 1e-5, what=f"4K one step, {lanes} lanes")
     say("4K one-step errors", e)
 
 
