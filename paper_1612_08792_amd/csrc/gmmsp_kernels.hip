@@ -466,8 +466,61 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     float* part = reinterpret_cast<float*>(P.part) + ((size_t)sub * P.n_cell + cell) * kPartStride;
     part[r] = acc[0];
     if (64 + r < kSlots * kStats) part[64 + r] = acc[1];
+  } else if (MODE == M_LABEL) {
+    // Eq. obtLi: rounds of 128 pixels, two per lane as in the statistics pass
+    // (the second masked past the end; a masked pixel evaluates the cell's
+    // first pixel and is neither stored nor counted)
+    __shared__ float s_off[kWavesPerBlock * kOffBlock];
+    float* woff = s_off + (threadIdx.x >> 6) * kOffBlock;
+    constexpr int kOffIdx[5] = {R_O1, R_O2, R_O3, R_O4, R_OL};
+    stage_offsets(woff, P.rec + (size_t)cell * (kSlots * kRecFloats), kRecFloats, kOffIdx, lane);
+    int r1 = lane / w, c1 = lane - r1 * w;
+    int r2 = (lane + 64) / w, c2 = (lane + 64) - r2 * w;
+    const int dr = 128 / w, dc = 128 - (128 / w) * w;
+    const int nx = Ip->nx;
+    for (int base = 0; base < npix; base += 128) {
+      int zero = 0;
+      asm volatile("" : "+s"(zero));
+      const AS4 float* rec = rec0 + zero;
+      const bool v1 = base + lane < npix, v2 = base + 64 + lane < npix;
+      const int y1 = v1 ? r1 : 0, x1 = v1 ? c1 : 0;
+      const int y2 = v2 ? r2 : y1, x2 = v2 ? c2 : x1;
+      const float* q1 = img + 3 * (y1 * W + x1);
+      const float* q2 = img + 3 * (y2 * W + x2);
+      const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
+      const float xr[2] = {(float)x1, (float)x2}, yr[2] = {(float)y1, (float)y2};
+      float e[2][kSlots], sum[2], shift[2];
+      int vz = 0;
+      asm volatile("" : "+v"(vz));
+      estep_pixels<2, true>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
+      int best[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        // the largest posterior, ties to the smallest k (slots ascend in k
+        // and the comparison is strict)
+        best[p] = 0;
+        float be = e[p][0];
+#pragma unroll
+        for (int s = 1; s < kSlots; ++s) {
+          if (e[p][s] > be) {
+            be = e[p][s];
+            best[p] = s;
+          }
+        }
+      }
+      if (v1)
+        out_i[pix0 + (int64_t)y1 * W + x1] =
+            (ccy + best[0] / 3 - 1) * nx + (ccx + best[0] % 3 - 1);
+      if (v2)
+        out_i[pix0 + (int64_t)y2 * W + x2] =
+            (ccy + best[1] / 3 - 1) * nx + (ccx + best[1] % 3 - 1);
+      llacc += v1 ? __builtin_amdgcn_logf(sum[0]) + shift[0] : 0.f;
+      llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;
+      advance(r1, c1, dr, dc, w);
+      advance(r2, c2, dr, dc, w);
+    }
   } else {
-    // one pixel per lane per step of 64
+    // the posteriors R (export), one pixel per lane per step of 64
     int row = lane / w, col = lane - (lane / w) * w;
     const int drow = 64 / w, dcol = 64 - (64 / w) * w;
     for (int p = lane; p < npix; p += 64) {
@@ -477,26 +530,9 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       float e[1][kSlots], sum[1], shift[1];
       estep_pixels<1>(rec, xr, yr, L, A, B, e, sum, shift);
       const float inv = __builtin_amdgcn_rcpf(sum[0]);
-      llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
-      if (MODE == M_LABEL) {
-        // Eq. obtLi: the largest posterior, ties to the smallest k (slots
-        // ascend in k and the comparison is strict)
-        int best = 0;
-        float be = e[0][0];
+      float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
 #pragma unroll
-        for (int s = 1; s < kSlots; ++s) {
-          if (e[0][s] > be) {
-            be = e[0][s];
-            best = s;
-          }
-        }
-        const int kx = ccx + (best % 3) - 1, ky = ccy + (best / 3) - 1;
-        out_i[pix0 + (int64_t)row * W + col] = ky * Ip->nx + kx;
-      } else if (MODE == M_EXPORT_R) {
-        float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) dst[s] = e[0][s] * inv;
-      }
+      for (int s = 0; s < kSlots; ++s) dst[s] = e[0][s] * inv;
       advance(row, col, drow, dcol, w);
     }
   }
