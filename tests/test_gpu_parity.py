@@ -299,3 +299,36 @@ def test_random_shapes_match_oracle(dev, seed):
     assert np.abs(out["R"] - Ro).max() <= 1e-4
     agree, _ = label_agreement(out["labels"], ref["labels"].reshape(-1), oracle_margin(ref["R"]))
     assert agree >= 0.999
+
+
+# ---------------------------------------------------------------------------
+# handle state errors (host checks before any launch)
+# ---------------------------------------------------------------------------
+def test_state_errors_leave_the_handle_usable(dev):
+    """EM, labels and the posterior export refuse a handle that has not been
+    initialised, and EM refuses a call that would run past the per-image history
+    of L(theta^t) (LL_CAP passes since the last initialisation).  Both are host
+    checks made before any launch, so the handle afterwards runs exactly as a
+    fresh one."""
+    from paper_1612_08792_amd import _lib
+    im = synth.voronoi_lab(97, 71, 5, 3.0, 21, 24)
+    lab = im.lab.reshape(-1).to(dev)
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    for call in (lambda: m.em_iterate(lab, 2), lambda: m.label(lab),
+                 lambda: m.export_responsibilities(lab)):
+        with pytest.raises(_lib.GmmspError) as err:
+            call()
+        assert err.value.code == _lib.GMMSP_E_STATE
+    m.init_seeds(lab)
+    with pytest.raises(_lib.GmmspError) as err:
+        m.em_iterate(lab, _lib.LL_CAP + 1)
+    assert err.value.code == _lib.GMMSP_E_STATE
+    m.em_iterate(lab, 3)
+    ref = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    ref.init_seeds(lab)
+    ref.em_iterate(lab, 3)
+    assert np.array_equal(m.get_params(), ref.get_params())
+    assert np.array_equal(m.ll_history(0), ref.ll_history(0))
+    la, lla = m.label(lab)
+    lb, llb = ref.label(lab)
+    assert torch.equal(la, lb) and lla[0] == llb[0]
