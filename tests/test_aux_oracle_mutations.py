@@ -1,0 +1,114 @@
+"""Planted mistakes in the oracles of the warm-start network, the colour front end
+and the accuracy measures, each of which one of their pins must catch (the same
+harness as ``test_oracle_mutations``: the mutant replaces one function on the CPU
+and at least one listed pin, over all its parameter sets, has to fail)."""
+import numpy as np
+import pytest
+
+import test_color_oracle as CP
+import test_metrics_oracle as MP
+import test_ws_oracle as WP
+from oracle import color_oracle as C
+from oracle import metrics_oracle as M
+from oracle import ws_oracle as WS
+from test_oracle_mutations import _pin_fails
+
+_conv, _bwd, _bf16 = WS.conv3x3, WS.conv3x3_backward, WS.bf16_round
+_br, _ue_asa = M.boundary_recall, M.ue_asa_sums
+
+
+def _conv_flipped(x, W, b):
+    """true convolution (taps mirrored) instead of the correlation of the kernels"""
+    return _conv(x, W[:, ::-1, :], b)
+
+
+def _bwd_dx_wrong_shift(x, W, dy_):
+    ny, nx, ci = x.shape
+    dxp = np.zeros((ny + 2, nx + 2, ci))
+    _, dW, db = _bwd(x, W, dy_)
+    for t, (dy, dx) in enumerate(WS.taps()):
+        dxp[1 - dy:1 - dy + ny, 1 - dx:1 - dx + nx] += dy_ @ W[:, t, :].astype(np.float64)
+    return dxp[1:-1, 1:-1], dW, db
+
+
+def _bwd_dw_unshifted(x, W, dy_):
+    dx, dW, db = _bwd(x, W, dy_)
+    dW = np.repeat(np.einsum("yxo,yxi->oi", dy_, x)[:, None, :], 9, axis=1)
+    return dx, dW, db
+
+
+def _bf16_truncate(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    return ((a.view(np.uint32) >> 16) << 16).view(np.float32)
+
+
+def _gamma_22(c):
+    return np.asarray(c, dtype=np.float64) ** 2.2
+
+
+def _lab_f_slope(t):
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(t > C.DELTA ** 3, np.cbrt(t), t / (C.DELTA ** 2) + 4.0 / 29.0)
+
+
+def _boundaries_right_only(labels):
+    b = np.zeros(labels.shape, bool)
+    b[:, :-1] |= labels[:, :-1] != labels[:, 1:]
+    return b
+
+
+def _recall_radius_one(sp, gt, r=2):
+    return _br(sp, gt, 1)
+
+
+def _ue_without_tolerance(sp, gt):
+    ov = M.overlaps(sp, gt)
+    size = {}
+    for (k, g), c in ov.items():
+        size[k] = size.get(k, 0) + c
+    return sum(size[k] for (k, g), c in ov.items()), _ue_asa(sp, gt)[1]
+
+
+def _asa_smallest_overlap(sp, gt):
+    ov = M.overlaps(sp, gt)
+    worst = {}
+    for (k, g), c in ov.items():
+        worst[k] = min(worst.get(k, c), c)
+    return _ue_asa(sp, gt)[0], sum(worst.values())
+
+
+MUTANTS = [
+    ("conv3x3 with mirrored taps", WS, "conv3x3", _conv_flipped,
+     [WP.test_conv3x3_matches_scipy_correlate, WP.test_backward_matches_finite_differences]),
+    ("data gradient shifted the wrong way", WS, "conv3x3_backward", _bwd_dx_wrong_shift,
+     [WP.test_backward_matches_finite_differences]),
+    ("weight gradient from the unshifted input", WS, "conv3x3_backward", _bwd_dw_unshifted,
+     [WP.test_backward_matches_finite_differences]),
+    ("bfloat16 by truncation, not round-to-nearest-even", WS, "bf16_round", _bf16_truncate,
+     [WP.test_bf16_round_matches_torch]),
+    ("sRGB decoded with a pure 2.2 power", C, "srgb_to_linear", _gamma_22,
+     [CP.test_reference_colours, CP.test_piecewise_functions_are_continuous]),
+    ("CIE f linear segment without its factor 3", C, "lab_f", _lab_f_slope,
+     [CP.test_piecewise_functions_are_continuous]),
+    ("D50 white instead of D65", C, "WHITE_D65", np.array([0.96422, 1.0, 0.82521]),
+     [CP.test_grey_axis_has_no_chroma, CP.test_reference_colours]),
+    ("boundary map without the lower neighbour", M, "boundaries", _boundaries_right_only,
+     [MP.test_boundary_recall_window_across_rows]),
+    ("boundary recall within one pixel, not two", M, "boundary_recall", _recall_radius_one,
+     [MP.test_boundary_recall_window]),
+    ("under-segmentation error without the 5 % tolerance", M, "ue_asa_sums",
+     _ue_without_tolerance, [MP.test_one_superpixel_over_two_regions]),
+    ("ASA with the smallest overlap", M, "ue_asa_sums", _asa_smallest_overlap,
+     [MP.test_one_superpixel_over_two_regions, MP.test_identical_maps_are_perfect]),
+]
+
+
+@pytest.mark.parametrize("what,mod,name,mutant,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(monkeypatch, what, mod, name, mutant, pins):
+    monkeypatch.setattr(mod, name, mutant)
+    assert any(_pin_fails(pin) for pin in pins), f"no pin caught: {what}"
+
+
+def test_pins_pass_on_the_oracles_themselves():
+    used = {pin for *_, pins in MUTANTS for pin in pins}
+    assert not [p.__name__ for p in used if _pin_fails(p)]

@@ -41,6 +41,17 @@ def test_boundary_recall_window(d, hit):
     assert total == 12 and hits == (12 if hit else 0)
 
 
+@pytest.mark.parametrize("d,hit", [(0, True), (2, True), (3, False), (-2, True), (-3, False)])
+def test_boundary_recall_window_across_rows(d, hit):
+    # the transposed case: a boundary between rows, found through the lower neighbour
+    gt = np.zeros((24, 12), np.int64)
+    gt[10:, :] = 1                                  # ground-truth boundary pixels at y = 9
+    sp = np.zeros_like(gt)
+    sp[10 + d:, :] = 1                              # superpixel boundary pixels at y = 9 + d
+    hits, total = M.boundary_recall(sp, gt)
+    assert total == 12 and hits == (12 if hit else 0)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_boundary_recall_by_distance_transform(seed):
     a = synth.voronoi_lab(70, 50, 15, 3.0, seed, 30).regions.numpy()
