@@ -1,20 +1,23 @@
-"""Planted mistakes in the oracles of the warm-start network, the colour front end
-and the accuracy measures, each of which one of their pins must catch (the same
+"""Planted mistakes in the oracles of the connectivity step, the warm-start
+network, the colour front end and the accuracy measures, each of which one of their pins must catch (the same
 harness as ``test_oracle_mutations``: the mutant replaces one function on the CPU
 and at least one listed pin, over all its parameter sets, has to fail)."""
 import numpy as np
 import pytest
 
 import test_color_oracle as CP
+import test_conn_oracle as KP
 import test_metrics_oracle as MP
 import test_ws_oracle as WP
 from oracle import color_oracle as C
+from oracle import conn_oracle as K
 from oracle import metrics_oracle as M
 from oracle import ws_oracle as WS
 from test_oracle_mutations import _pin_fails
 
 _conv, _bwd, _bf16 = WS.conv3x3, WS.conv3x3_backward, WS.bf16_round
 _br, _ue_asa = M.boundary_recall, M.ue_asa_sums
+_segments, _seg_colours = K.segments, K.segment_colours
 
 
 def _conv_flipped(x, W, b):
@@ -77,7 +80,46 @@ def _asa_smallest_overlap(sp, gt):
     return _ue_asa(sp, gt)[0], sum(worst.values())
 
 
+def _segments_8_connected(labels):
+    H, W = labels.shape
+    seg = np.full((H, W), -1, dtype=np.int64)
+    ids = []
+    for y0 in range(H):
+        for x0 in range(W):
+            if seg[y0, x0] >= 0:
+                continue
+            sid = y0 * W + x0
+            ids.append(sid)
+            seg[y0, x0] = sid
+            stack = [(y0, x0)]
+            while stack:
+                y, x = stack.pop()
+                for yy in (y - 1, y, y + 1):
+                    for xx in (x - 1, x, x + 1):
+                        if (0 <= yy < H and 0 <= xx < W and seg[yy, xx] < 0
+                                and labels[yy, xx] == labels[y0, x0]):
+                            seg[yy, xx] = sid
+                            stack.append((yy, xx))
+    return seg, ids
+
+
+def _colour_sums_not_means(lab, seg, ids):
+    size, col = _seg_colours(lab, seg, ids)
+    return size, {s: tuple(c * size[s] for c in col[s]) for s in ids}
+
+
+def _distance_without_b(a, b):
+    dL, da = a[0] - b[0], a[1] - b[1]
+    return dL * dL + da * da
+
+
 MUTANTS = [
+    ("8- instead of 4-connected segments", K, "segments", _segments_8_connected,
+     [KP.test_segments_match_scipy, KP.test_invariants_on_fragmented_labels]),
+    ("segment colour sums instead of means", K, "segment_colours", _colour_sums_not_means,
+     [KP.test_quantised_means_are_the_means, KP.test_fragment_joins_the_closer_colour]),
+    ("colour distance without the b* term", K, "colour_dist2", _distance_without_b,
+     [KP.test_colour_distance_counts_a_and_b]),
     ("conv3x3 with mirrored taps", WS, "conv3x3", _conv_flipped,
      [WP.test_conv3x3_matches_scipy_correlate, WP.test_backward_matches_finite_differences]),
     ("data gradient shifted the wrong way", WS, "conv3x3_backward", _bwd_dx_wrong_shift,

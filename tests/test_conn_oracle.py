@@ -78,6 +78,22 @@ def test_fragment_joins_the_closer_colour():
     assert np.all(out[:, :6][labels[:, :6] == 0] == 0)
 
 
+def test_colour_distance_counts_a_and_b():
+    # equal L everywhere; the right half differs from the left only in a* (then
+    # only in b*), and the fragment is 2 from the right half and 8 from the left
+    # in that channel alone, so it must join the right half both times
+    for ch in (1, 2):
+        labels = np.zeros((12, 12), np.int64)
+        labels[:, 6:] = 1
+        labels[5:7, 5:7] = 2
+        lab = flat_image(12, 12, 50.0)
+        lab[:, 6:, ch] = 10.0
+        lab[5:7, 5:7, ch] = 8.0
+        out, info = C.enforce_connectivity(labels, lab, 6, 6)
+        assert info["merged"] == 1, ch
+        assert np.all(out[5:7, 5:7] == 6), ch
+
+
 def test_size_update_keeps_a_grown_segment():
     # A (2 px, L 50) merges into B (7 px, L 52); B then has 9 px, 4 * 9 >= 36,
     # so B stays although its own 7 px are below a quarter of 6 x 6
