@@ -18,6 +18,7 @@ from test_oracle_mutations import _pin_fails
 _conv, _bwd, _bf16 = WS.conv3x3, WS.conv3x3_backward, WS.bf16_round
 _br, _ue_asa = M.boundary_recall, M.ue_asa_sums
 _segments, _seg_colours = K.segments, K.segment_colours
+_features, _theta0, _targets = WS.features, WS.theta0_rows, WS.targets
 
 
 def _conv_flipped(x, W, b):
@@ -113,6 +114,42 @@ def _distance_without_b(a, b):
     return dL * dL + da * da
 
 
+def _features_uncapped(lab, vx, vy, nx, ny):
+    f = _features(lab, vx, vy, nx, ny)
+    for ky in range(ny):
+        for kx in range(nx):
+            f[ky, kx, 6] = min(kx, ky, nx - 1 - kx, ny - 1 - ky) / 3.0
+    return f
+
+
+def _features_sample_std(lab, vx, vy, nx, ny):
+    f = _features(lab, vx, vy, nx, ny)
+    lab = np.asarray(lab, dtype=np.float64)
+    for ky in range(ny):
+        for kx in range(nx):
+            px = lab[ky * vy:(ky + 1) * vy, kx * vx:(kx + 1) * vx].reshape(-1, 3)
+            f[ky, kx, 3:6] = px.std(axis=0, ddof=1) / 16.0
+    return f
+
+
+def _features_half_cells_reversed(lab, vx, vy, nx, ny):
+    f = _features(lab, vx, vy, nx, ny)
+    f[..., 10:16] *= -1.0
+    return f
+
+
+def _theta0_log_variance(out, lab, vx, vy, lam, mask=WS.ALL_OUTPUTS):
+    o = np.array(out, dtype=np.float64)
+    o[..., 5:10] *= 0.5           # e^(s) where the law has e^(2 s)
+    return _theta0(o, lab, vx, vy, lam, mask)
+
+
+def _targets_log_variance(rows, lab, vx, vy, nx, ny, lam):
+    t = _targets(rows, lab, vx, vy, nx, ny, lam)
+    t[..., 5:10] *= 2.0
+    return t
+
+
 MUTANTS = [
     ("8- instead of 4-connected segments", K, "segments", _segments_8_connected,
      [KP.test_segments_match_scipy, KP.test_invariants_on_fragmented_labels]),
@@ -120,6 +157,12 @@ MUTANTS = [
      [KP.test_quantised_means_are_the_means, KP.test_fragment_joins_the_closer_colour]),
     ("colour distance without the b* term", K, "colour_dist2", _distance_without_b,
      [KP.test_colour_distance_counts_a_and_b]),
+    ("border channel without its cap at 3 cells", WS, "features", _features_uncapped,
+     [WP.test_border_channel_caps_at_three]),
+    ("cell standard deviation with N - 1", WS, "features", _features_sample_std,
+     [WP.test_half_cell_and_seed_channels_by_hand]),
+    ("half-cell differences left minus right", WS, "features", _features_half_cells_reversed,
+     [WP.test_half_cell_and_seed_channels_by_hand]),
     ("conv3x3 with mirrored taps", WS, "conv3x3", _conv_flipped,
      [WP.test_conv3x3_matches_scipy_correlate, WP.test_backward_matches_finite_differences]),
     ("data gradient shifted the wrong way", WS, "conv3x3_backward", _bwd_dx_wrong_shift,
@@ -154,3 +197,12 @@ def test_pins_catch_planted_mistake(monkeypatch, what, mod, name, mutant, pins):
 def test_pins_pass_on_the_oracles_themselves():
     used = {pin for *_, pins in MUTANTS for pin in pins}
     assert not [p.__name__ for p in used if _pin_fails(p)]
+
+
+def test_log_variance_reading_in_both_directions_is_caught(monkeypatch):
+    """Outputs read as log-variances in theta^0 and in the targets alike: the two
+    stay inverse to each other, so only the hand pin of the scale law catches it."""
+    monkeypatch.setattr(WS, "theta0_rows", _theta0_log_variance)
+    monkeypatch.setattr(WS, "targets", _targets_log_variance)
+    assert not _pin_fails(WP.test_targets_invert_theta0)
+    assert _pin_fails(WP.test_log_scales_are_log_standard_deviations)

@@ -1,6 +1,8 @@
 """Pins of the warm-start network oracle: convolution against scipy, backward
 against central finite differences, bfloat16 rounding against torch, and the
 exact inverse relation between targets and theta^0."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -66,6 +68,16 @@ def test_features_of_constant_cells_and_border_channel():
     np.testing.assert_allclose(f[..., 6] * 3, [[0, 0, 0, 0, 0], [0, 1, 1, 1, 0], [0, 0, 0, 0, 0]])
 
 
+def test_border_channel_caps_at_three():
+    # a 9 x 9 grid of 2 x 2 cells: the centre cell is 4 cells from every border,
+    # capped at 3; the ring next to the border is 1
+    f = WS.features(np.zeros((18, 18, 3), np.float32), 2, 2, 9, 9)
+    d = np.minimum(np.minimum(np.arange(9)[:, None], np.arange(9)[None, :]),
+                   np.minimum(8 - np.arange(9)[:, None], 8 - np.arange(9)[None, :]))
+    np.testing.assert_allclose(f[..., 6] * 3, np.minimum(d, 3))
+    assert f[4, 4, 6] == 1.0
+
+
 def test_half_cell_and_seed_channels_by_hand():
     # one 5 x 5 cell: L = 10 x (column), a = 4 x (row), b = 0; h = 2
     lab = np.zeros((5, 5, 3), np.float32)
@@ -88,6 +100,19 @@ def test_zero_output_is_the_grid_init():
     np.testing.assert_array_equal(rows[4, 2:5], lab[28, 28])
     np.testing.assert_allclose(rows[:, [5, 7, 8, 9, 11]], [[361, 361, 64, 64, 64]] * 6)
     assert np.all(rows[:, [6, 10]] == 0)
+
+
+def test_log_scales_are_log_standard_deviations():
+    # Sigma^0 = diag(v_x^2 e^(2 s_x), v_y^2 e^(2 s_y), lambda^2 e^(2 s_L), ...): an
+    # output s = ln 2 doubles the standard deviation (four times the variance),
+    # and a mean output of 1/2 moves the mean by half a cell / half of lambda
+    lab = np.zeros((20, 30, 3), np.float32)
+    out = np.zeros((2, 3, 10))
+    out[1, 2] = [0.5, -0.5, 0.5, 0, 0, math.log(2), 0, 0, math.log(2), 0]
+    rows = WS.theta0_rows(out, lab, 10, 10, 8.0)
+    r = rows[1 * 3 + 2]
+    assert r[0] == 25 + 5 and r[1] == 15 - 5 and r[2] == 4.0
+    np.testing.assert_allclose(r[[5, 7, 8, 9, 11]], [400, 100, 64, 256, 64], rtol=1e-12)
 
 
 def test_output_mask_zeroes_outputs():
