@@ -12,12 +12,14 @@ import math
 import numpy as np
 import pytest
 
+import test_oracle_modes as MODES
 import test_oracle_pins as PINS
 from oracle import gmm_oracle as O
 
 _orig = {name: getattr(O, name) for name in (
     "log_density_pairs", "estep", "clamp_eigen", "mstep_one", "make_grid", "window",
-    "labels_from", "init_theta", "seed_index", "block_eps")}
+    "labels_from", "init_theta", "seed_index", "block_eps", "clamp_eigen_scaled",
+    "component_floors")}
 
 
 _PARAM_SET = type(pytest.param(0))
@@ -153,6 +155,25 @@ def _colour_floor_spatial(cov_mode, p):
     return [p.eps_s for _ in _orig["block_eps"](cov_mode, p)]
 
 
+def _scaled_floor_unscaled_back(S, floors):
+    """floors applied in the scaled coordinates but the result not scaled back"""
+    f = np.sqrt(np.asarray(floors, dtype=np.float64))
+    w, Q = np.linalg.eigh(S / np.outer(f, f))
+    return (Q * np.maximum(w, 1.0)[None, :]) @ Q.T
+
+
+def _scaled_floor_by_floors(S, floors):
+    """scaled by the floors themselves instead of their square roots"""
+    f = np.asarray(floors, dtype=np.float64)
+    w, Q = np.linalg.eigh(S / np.outer(f, f))
+    return np.outer(f, f) * ((Q * np.maximum(w, 1.0)[None, :]) @ Q.T)
+
+
+def _floors_colour_first(cov_mode, p):
+    fl = _orig["component_floors"](cov_mode, p)
+    return fl[::-1].copy()
+
+
 MUTANTS = [
     ("ln det Sigma dropped from the log density", "log_density_pairs", _logdet_dropped,
      [PINS.test_log_density_matches_scipy]),
@@ -188,6 +209,16 @@ MUTANTS = [
      [PINS.test_init_seed_pixels_hand_values]),
     ("colour blocks floored with the spatial epsilon", "block_eps", _colour_floor_spatial,
      [PINS.test_separated_blocks_are_recovered]),
+    ("full-Sigma floor not scaled back", "clamp_eigen_scaled", _scaled_floor_unscaled_back,
+     [MODES.test_scaled_floor_is_the_block_rule_on_block_diagonal_sigma,
+      MODES.test_scaled_floor_properties]),
+    ("full-Sigma floor scaled by the floors, not their roots", "clamp_eigen_scaled",
+     _scaled_floor_by_floors,
+     [MODES.test_scaled_floor_is_the_block_rule_on_block_diagonal_sigma,
+      MODES.test_scaled_floor_properties]),
+    ("component floors in the wrong order", "component_floors", _floors_colour_first,
+     [MODES.test_scaled_floor_is_the_block_rule_on_block_diagonal_sigma,
+      MODES.test_scaled_floor_maximises_the_constrained_likelihood]),
 ]
 
 
