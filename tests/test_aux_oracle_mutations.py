@@ -175,6 +175,8 @@ MUTANTS = [
      [CP.test_reference_colours, CP.test_piecewise_functions_are_continuous]),
     ("CIE f linear segment without its factor 3", C, "lab_f", _lab_f_slope,
      [CP.test_piecewise_functions_are_continuous]),
+    ("sRGB-to-XYZ matrix transposed", C, "M_RGB_TO_XYZ", np.ascontiguousarray(C.M_RGB_TO_XYZ.T),
+     [CP.test_reference_colours, CP.test_grey_axis_has_no_chroma]),
     ("D50 white instead of D65", C, "WHITE_D65", np.array([0.96422, 1.0, 0.82521]),
      [CP.test_grey_axis_has_no_chroma, CP.test_reference_colours]),
     ("boundary map without the lower neighbour", M, "boundaries", _boundaries_right_only,
