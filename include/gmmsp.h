@@ -187,6 +187,19 @@ int gmmsp_export_candidates(gmmsp_handle* h, int32_t* cand_dev, void* stream);
 int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell);
 int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
 
+/* Work split of the statistics pass (E-step of Eqs. gaussian and Rik with the
+ * sums of Eqs. UpdateMu .. UpdateSigC), cov_mode 0 only.  kind 0: every lane of
+ * a cell's wave takes whole pixels and evaluates all nine candidates of each;
+ * kind 1 (the default where it applies): every lane takes one candidate slot
+ * and one column phase of the cell, so the slot's Gaussian stays in that lane's
+ * registers, and the nine densities of a pixel meet in LDS for the normalisation
+ * of Eq. Rik.  Kind 1 covers cells up to 56 pixels wide (v_x <= 56); E_INVAL for
+ * kind 1 with another cov_mode or a wider grid.  Both give the method's result
+ * (FP32 arithmetic, FP64 gather; they differ in the rounding of the FP32 sums)
+ * and each is bitwise repeatable. */
+int gmmsp_set_estep_kernel(gmmsp_handle* h, int32_t kind);
+int gmmsp_get_estep_kernel(const gmmsp_handle* h, int32_t* kind);
+
 /* Autotuner: times `passes` statistics passes (after three untimed passes)
  * from the grid initialisation for each schedule 1, 2, 4 with HIP events on
  * `stream`; a schedule with more waves is kept only if it is more than 3 %

@@ -61,6 +61,8 @@ _SIGS = {
     "gmmsp_export_candidates": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmmsp_set_schedule": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_schedule": (c_int, [c_void_p, POINTER(c_int32)]),
+    "gmmsp_set_estep_kernel": (c_int, [c_void_p, c_int32]),
+    "gmmsp_get_estep_kernel": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_autotune": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32), c_void_p]),
     "gmmsp_set_gather_lanes": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_gather_lanes": (c_int, [c_void_p, POINTER(c_int32)]),

@@ -14,7 +14,7 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature",
                 "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]
-SOURCES = ["gmmsp_kernels.hip", "gmmsp_cov3.hip", "gmmsp_modes.hip", "gmmsp_warmstart.hip", "gmmsp_connect.hip", "gmmsp_metrics.hip", "gmmsp_color.hip", "gmmsp_api.cpp"]
+SOURCES = ["gmmsp_kernels.hip", "gmmsp_slots.hip", "gmmsp_cov3.hip", "gmmsp_modes.hip", "gmmsp_warmstart.hip", "gmmsp_connect.hip", "gmmsp_metrics.hip", "gmmsp_color.hip", "gmmsp_api.cpp"]
 
 
 def build(verbose: bool = False) -> str:

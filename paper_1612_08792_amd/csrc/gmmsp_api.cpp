@@ -199,7 +199,7 @@ struct gmmsp_handle {
   hipGraphExec_t gexec = nullptr;
   const float* g_lab = nullptr;
   double g_tol = 0.0;
-  int32_t g_len = 0, g_wpc = 0;
+  int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1;
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -297,6 +297,12 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.wpc = 1;
   P.glanes = 1;
   P.cov_mode = L.cov_mode;
+  // the slot-lane statistics pass covers cells up to 56 pixels wide (split
+  // colour blocks only); otherwise the pixel-lane pass runs
+  int32_t max_vx = 0;
+  for (const ImgDesc& d : descs) max_vx = std::max(max_vx, d.vx);
+  P.estep = 0;
+  if (P.cov_mode == 0 && slots_shape(max_vx, &P.slot_j, &P.slot_rc)) P.estep = 1;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -417,6 +423,8 @@ int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t le
   h->g_tol = rel_tol;
   h->g_len = len;
   h->g_wpc = h->P.wpc;
+  h->g_glanes = h->P.glanes;
+  h->g_estep = h->P.estep;
   return GMMSP_OK;
 }
 
@@ -430,7 +438,9 @@ int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, doubl
   if (e == hipSuccess && !h->gev_out) e = hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming);
   if (e != hipSuccess) return hip_fail(e, "graph stream");
   const int32_t G = h->graph_passes;
-  if (!h->gexec || h->g_lab != lab || h->g_tol != rel_tol || h->g_len != G || h->g_wpc != h->P.wpc) {
+  // the graph holds the kernels and arguments of the schedule it was captured with
+  if (!h->gexec || h->g_lab != lab || h->g_tol != rel_tol || h->g_len != G || h->g_wpc != h->P.wpc ||
+      h->g_glanes != h->P.glanes || h->g_estep != h->P.estep) {
     int rc = capture_passes(h, lab, rel_tol, G);
     if (rc) return rc;
   }
@@ -610,6 +620,23 @@ int gmmsp_set_schedule(gmmsp_handle* h, int32_t waves_per_cell) {
 int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell) {
   if (!h || !waves_per_cell) return fail(GMMSP_E_INVAL, "null pointer");
   *waves_per_cell = h->P.wpc;
+  return GMMSP_OK;
+}
+
+int gmmsp_set_estep_kernel(gmmsp_handle* h, int32_t kind) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (kind != 0 && kind != 1) return fail(GMMSP_E_INVAL, "statistics pass kind must be 0 or 1");
+  if (kind == 1) {
+    if (h->P.cov_mode != 0) return fail(GMMSP_E_INVAL, "the slot-lane pass needs cov_mode 0");
+    if (!h->P.slot_j) return fail(GMMSP_E_INVAL, "the slot-lane pass covers cells up to 56 pixels wide");
+  }
+  h->P.estep = kind;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_estep_kernel(const gmmsp_handle* h, int32_t* kind) {
+  if (!h || !kind) return fail(GMMSP_E_INVAL, "null pointer");
+  *kind = h->P.estep;
   return GMMSP_OK;
 }
 

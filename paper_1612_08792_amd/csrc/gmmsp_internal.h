@@ -109,6 +109,10 @@ struct DevPtrs {
   int32_t glanes;           // lanes per superpixel of the gather (1, 4 or 16)
   int32_t cov_mode;         // 0 split colour blocks; 1 3x3 colour block (gmmsp_cov3.hip);
                             // 2 full 5x5, 3 grayscale (gmmsp_modes.hip)
+  int32_t estep;            // statistics pass of the split colour blocks: 0 one pixel per
+                            // lane (k_cells), 1 one candidate slot per lane (k_slots,
+                            // gmmsp_slots.hip; its colour statistics are whitened)
+  int32_t slot_j, slot_rc;  // k_slots shape: columns per lane, rows per chunk
 };
 
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
@@ -122,6 +126,12 @@ hipError_t launch_finalize(const DevPtrs& P, hipStream_t s);
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s);
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s);
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
+
+// The slot-lane statistics pass (gmmsp_slots.hip).  slots_shape gives the
+// columns per lane and rows per chunk for cells up to max_w pixels wide (0 when
+// the kernel does not cover that width).
+int slots_shape(int max_w, int* J, int* RC);
+hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s);
 
 // The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
 // 2 responsibilities, 3 candidates.

@@ -634,23 +634,58 @@ __device__ inline void add_cell_stats(const DevPtrs& P, const ImgDesc& I, int kx
   }
 }
 
+// Colour factors of a superpixel's record (its own cell, slot 4), in FP64:
+// w = SL L + OL, u1 = A11 a + A12 b + O3, u2 = A22 b + O4.  The slot-lane
+// statistics pass takes the colour moments in these coordinates.
+struct ColourFrame {
+  double sl, ol, a11, a12, a22, o3, o4;
+};
+
+__device__ inline ColourFrame colour_frame(const DevPtrs& P, const ImgDesc& I, const SpDesc& d) {
+  const float* f = P.rec + ((size_t)(I.cell_off + d.ky * I.ncx + d.kx) * kSlots + 4) * kRecFloats;
+  return ColourFrame{f[R_SL], f[R_OL], f[R_A11], f[R_A12], f[R_A22], f[R_O3], f[R_O4]};
+}
+
 // theta^{t+1} of superpixel d from its window statistics: the mean (Eq.
 // UpdateMu), the block covariances about it (Eqs. UpdateSigS, UpdateSigC) and
 // the shape control; false when the mass is below n_min (theta^t is kept).
-// row is the superpixel's FP64 master row (the colour moments were taken
-// about its float32 mean).
-__device__ inline bool theta_from_stats(const double (&acc)[kStats], const SpDesc& d,
-                                        const ImgDesc& I, const double* row, SpTheta& q) {
+// The colour moments are about the superpixel's float32 mean (row: its FP64
+// master row), or, with cf, whitened moments in the frame cf, which are mapped
+// back to Lab first: d_L = w / SL, d_b = u2 / A22, d_a = (u1 - A12 d_b) / A11,
+// about the colour at which w, u1 and u2 vanish.
+__device__ inline bool theta_from_stats(double (&acc)[kStats], const SpDesc& d,
+                                        const ImgDesc& I, const double* row, SpTheta& q,
+                                        const ColourFrame* cf) {
   const double N = acc[S_N];
   if (!(N >= I.n_min)) return false;
+  double oL, oa, ob;
+  if (cf) {
+    const double k = cf->a12 / cf->a22;
+    const double sw = acc[S_L], s1 = acc[S_A], s2 = acc[S_B];
+    const double sww = acc[S_LL], s11 = acc[S_AA], s12 = acc[S_AB], s22 = acc[S_BB];
+    acc[S_L] = sw / cf->sl;
+    acc[S_B] = s2 / cf->a22;
+    acc[S_A] = (s1 - k * s2) / cf->a11;
+    acc[S_LL] = sww / (cf->sl * cf->sl);
+    acc[S_BB] = s22 / (cf->a22 * cf->a22);
+    acc[S_AB] = (s12 - k * s22) / (cf->a11 * cf->a22);
+    acc[S_AA] = (s11 - 2.0 * k * s12 + k * k * s22) / (cf->a11 * cf->a11);
+    oL = -cf->ol / cf->sl;
+    ob = -cf->o4 / cf->a22;
+    oa = (-cf->o3 - cf->a12 * ob) / cf->a11;
+  } else {
+    oL = (double)(float)row[2];
+    oa = (double)(float)row[3];
+    ob = (double)(float)row[4];
+  }
   const double iN = 1.0 / N;
   const double mx = acc[S_X] * iN, my = acc[S_Y] * iN;
   const double mL = acc[S_L] * iN, ma = acc[S_A] * iN, mb = acc[S_B] * iN;
   q.mx = (double)d.kx * I.vx + mx;
   q.my = (double)d.ky * I.vy + my;
-  q.mL = (double)(float)row[2] + mL;
-  q.ma = (double)(float)row[3] + ma;
-  q.mb = (double)(float)row[4] + mb;
+  q.mL = oL + mL;
+  q.ma = oa + ma;
+  q.mb = ob + mb;
   const Sym2 s = clamp2(acc[S_XX] * iN - mx * mx, acc[S_XY] * iN - mx * my,
                         acc[S_YY] * iN - my * my, I.eps_s);
   const Sym2 c = clamp2(acc[S_AA] * iN - ma * ma, acc[S_AB] * iN - ma * mb,
@@ -677,7 +712,9 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
     for (int dx = -1; dx <= 1; ++dx) add_cell_stats(P, I, d.kx, d.ky, dx, dy, acc);
   double* row = P.theta + (size_t)sp * kThetaRow;
   SpTheta q;
-  if (!theta_from_stats(acc, d, I, row, q)) {
+  ColourFrame cf;
+  if (P.estep == 1) cf = colour_frame(P, I, d);
+  if (!theta_from_stats(acc, d, I, row, q, P.estep == 1 ? &cf : nullptr)) {
     row[12] = acc[S_N];  // 0/0 guard: theta_k keeps its value
     return;
   }
@@ -710,12 +747,15 @@ __global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P) {
     for (int j = 0; j < kStats; ++j) acc[j] += __shfl_xor(acc[j], m, G);
   double* row = P.theta + (size_t)sp * kThetaRow;
   SpTheta q;
-  const bool ok = theta_from_stats(acc, d, I, row, q);
+  ColourFrame cf;
+  if (P.estep == 1) cf = colour_frame(P, I, d);
+  const bool ok = theta_from_stats(acc, d, I, row, q, P.estep == 1 ? &cf : nullptr);
   if (!ok) {
     if (lane == 0) row[12] = acc[S_N];  // 0/0 guard: theta_k keeps its value
     return;
   }
-  // every lane has read row[2..4] inside theta_from_stats before lane 0 rewrites it
+  // every lane has read row[2..4] and the record's colour frame before lane 0
+  // rewrites the row and the lanes rewrite the records
   __builtin_amdgcn_wave_barrier();
   if (lane == 0) store_theta_row(row, q, acc[S_N]);
   for (int c = lane; c < kSlots; c += G) write_record_slot(P, I, d.kx, d.ky, q, c % 3 - 1, c / 3 - 1);
@@ -754,6 +794,7 @@ hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
   if (P.cov_mode) return launch_alt_cells(P, 0, lab, nullptr, nullptr, s);
+  if (P.estep == 1) return launch_estep_slots(P, lab, s);
   const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
   if (P.wpc == 4)
     hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,

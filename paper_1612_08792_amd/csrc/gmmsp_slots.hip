@@ -1,0 +1,382 @@
+// Slot-lane E-step with fused M-step statistics, for the split colour blocks
+// (Eqs. gaussian, Rik; the numerators and denominators of Eqs. UpdateMu,
+// UpdateSigS, UpdateSigC).
+//
+// Work decomposition.  One 64-lane wave owns one v_x x v_y cell (Eq. Ik: all
+// pixels of a cell share the candidate set of the 3 x 3 neighbouring seeds).
+// Lane l owns candidate slot s = l / 7 and column phase q = l % 7 (lane 63
+// idles): it evaluates slot s for the cell pixels of columns q, q + 7, ...,
+// so the slot's record factors live in the lane's own vector registers and
+// every density and statistics instruction reads vector registers only (on
+// gfx950 such instructions issue at twice the rate of those that read a
+// scalar register).  Rows are processed in chunks of RC rows:
+//   phase 0  one lane per pixel stages the chunk's pixels in the wave's LDS;
+//   phase 1  every (slot, phase) lane evaluates its slot's log density for
+//            its RC x J pixels, exponentiates and writes e = 2^l to LDS;
+//   phase 2  one lane per pixel adds the nine e of its pixel (Eq. Rik's
+//            denominator), takes the reciprocal and the log-likelihood term;
+//   phase 3  every (slot, phase) lane forms R = e / sum for its pixels and
+//            adds them to its slot's statistics.
+// Spatial statistics use per-column accumulators (a lane's columns are fixed,
+// its row is wave-uniform); colour statistics are taken in the record's
+// whitened colour coordinates (w, u1, u2), which the density computes anyway,
+// and are mapped back to Lab by the FP64 gather.  At the end of the cell the
+// seven lanes of each slot are added in a fixed order through LDS.
+#include "gmmsp_internal.h"
+#include "gmmsp_wave.h"
+
+#include <math.h>
+
+namespace gmmsp {
+
+namespace {
+
+constexpr int kQ = 7;  // column phases per slot: 9 x 7 = 63 lanes
+
+// LDS of one wave for J columns per lane and RC rows per chunk.
+template <int J, int RC>
+struct SlotLds {
+  static constexpr int kPB = ((RC * J * 3 + 3) / 4) * 4;  // pixel floats per column phase
+  static constexpr int kEB = ((RC * J + 3) / 4) * 4;      // e floats per (slot, phase)
+  static constexpr int kPix = kQ * kPB;
+  static constexpr int kE = (kSlots + 1) * kQ * kEB;       // + the idle lane's row
+  static constexpr int kInv = kQ * kEB;
+  static constexpr int kRed = 64 * kStats;                 // end-of-cell reduction
+  static constexpr int kTail = kE + 2 * kInv > kRed ? kE + 2 * kInv : kRed;
+  static constexpr int kWave = kPix + kTail;
+};
+
+// LDS writes of this wave become visible to all of its lanes
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// keep a wave-uniform value in a vector register, so that the instructions
+// that read it stay in the all-vector-register form
+__device__ __forceinline__ float vreg(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+}  // namespace
+
+template <int J, int RC, int WPC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
+    DevPtrs P, const float* __restrict__ lab) {
+  // products are rounded where written: every shape of the kernel rounds alike
+#pragma clang fp contract(off)
+  using LL = SlotLds<J, RC>;
+  __shared__ __align__(16) float lds[kWavesPerBlock * LL::kWave];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  float* PIX = lds + wv * LL::kWave;
+  float* E = PIX + LL::kPix;
+  float* INV = E + LL::kE;
+  float* SH = INV + LL::kInv;
+  float* RED = E;
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + wv));
+  const int cell = __builtin_amdgcn_readfirstlane(gw / WPC);
+  const int sub = __builtin_amdgcn_readfirstlane(gw - cell * WPC);
+  if (cell >= P.n_cell) return;
+  const AS4 CellDesc* cdp = cptr(P.cell) + cell;
+  const int b = cdp->img, ccx = cdp->cx, ccy = cdp->cy;
+  if (cptr(P.state)[b].done) return;
+  const AS4 ImgDesc* Ip = cptr(P.img) + b;
+  const int W = Ip->W, H = Ip->H, vx = Ip->vx, vy = Ip->vy;
+  const int x0 = ccx * vx, y0 = ccy * vy;
+  const int w = min(vx, W - x0), h = min(vy, H - y0);
+  const float* img = lab + 3 * (Ip->pix_off + (int64_t)y0 * W + x0);
+
+  // this lane's slot and column phase; lane 63 idles on a copy of slot 8
+  const int s = lane / kQ;
+  const int q = lane - kQ * s;
+  const bool live = s < kSlots;
+  const float4* rp = reinterpret_cast<const float4*>(
+      P.rec + ((size_t)cell * kSlots + (live ? s : kSlots - 1)) * kRecFloats);
+  const float4 f0 = rp[0], f1 = rp[1], f2 = rp[2], f3 = rp[3];
+  const float L11 = f0.x, L12 = f0.y, O1 = f0.z, O2 = f0.w;
+  const float L22 = f1.x, SL = f1.y, O3 = f1.z, O4 = f1.w;
+  const float OL = f2.x, A11 = f2.y, A12 = f2.z, A22 = f2.w;
+  const float C = f3.x;
+  // t1 = L11 x + L12 y + O1 = ax[j] + L12 y for the lane's column x = q + 7 j;
+  // a column outside the cell (or the idle lane) gets +inf, so its density is 0
+  float ax[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = q + kQ * j;
+    ax[j] = (live && c < w) ? fmaf(L11, (float)c, O1) : INFINITY;
+  }
+
+  // the pixel this lane stages and normalises in phases 0 and 2
+  const int p_r = lane / w;
+  const int p_c = lane - p_r * w;
+  const int p_q = p_c % kQ, p_j = p_c / kQ;
+  const int p_e = p_q * LL::kEB + p_r * J + p_j;        // index in E (slot 0), INV, SH
+  const int p_x = p_q * LL::kPB + (p_r * J + p_j) * 3;  // index in PIX
+
+  // entries that no pixel writes stay finite (0): a masked column reads them
+  for (int i = lane; i < LL::kPix; i += 64) PIX[i] = 0.f;
+  for (int i = lane; i < 2 * LL::kInv; i += 64) INV[i] = 0.f;
+
+  float Nj[J], Mj[J], Qj[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) Nj[j] = Mj[j] = Qj[j] = 0.f;
+  float Sw = 0.f, Su1 = 0.f, Su2 = 0.f, Sww = 0.f, S11 = 0.f, S12 = 0.f, S22 = 0.f;
+  double ll64 = 0.0;  // sum of the pixels' log2 terms, in units of 2^-22
+
+  const int n_chunks = (h + RC - 1) / RC;
+  // prefetch of the first chunk's pixel
+  float pf0 = 0.f, pf1 = 0.f, pf2 = 0.f;
+  if (sub < n_chunks && p_r < min(RC, h - sub * RC)) {
+    const float* src = img + 3 * ((sub * RC + p_r) * W + p_c);
+    pf0 = src[0];
+    pf1 = src[1];
+    pf2 = src[2];
+  }
+  for (int ch = sub; ch < n_chunks; ch += WPC) {
+    const int r0 = ch * RC;
+    const int nr = min(RC, h - r0);
+    // phase 0: stage this chunk's pixels, then fetch the next chunk's
+    wave_sync();  // the previous chunk's reads of PIX are done
+    if (p_r < nr) {
+      PIX[p_x] = pf0;
+      PIX[p_x + 1] = pf1;
+      PIX[p_x + 2] = pf2;
+    }
+    wave_sync();
+    {
+      const int cn = ch + WPC;
+      if (cn < n_chunks && p_r < min(RC, h - cn * RC)) {
+        const float* src = img + 3 * ((cn * RC + p_r) * W + p_c);
+        pf0 = src[0];
+        pf1 = src[1];
+        pf2 = src[2];
+      }
+    }
+    // phase 1: log densities (log2 units, Eq. gaussian) and e = 2^l
+    float e[RC][J], tw[RC][J], tu1[RC][J], tu2[RC][J];
+    float cr[RC], rrv[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      rrv[i] = vreg((float)(r0 + i));
+      const float t2 = fmaf(L22, rrv[i], O2);
+      // a row past the cell's end gets -inf (a wave-uniform addend, no select)
+      const float rowoff = i < nr ? 0.f : -INFINITY;
+      cr[i] = fmaf(-t2, t2, C) + rowoff;
+      const float* px = PIX + q * LL::kPB + i * J * 3;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const float Lv = px[3 * j], Av = px[3 * j + 1], Bv = px[3 * j + 2];
+        tw[i][j] = fmaf(SL, Lv, OL);
+        tu1[i][j] = fmaf(A11, Av, fmaf(A12, Bv, O3));
+        tu2[i][j] = fmaf(A22, Bv, O4);
+      }
+    }
+    // l = C - t1^2 - t2^2 - w^2 - u1^2 - u2^2 with t1 = L11 x + L12 y + O1
+    auto log_density = [&](int i, int j) {
+      const float t1 = fmaf(L12, rrv[i], ax[j]);
+      float qq = t1 * t1;
+      qq = fmaf(tw[i][j], tw[i][j], qq);
+      qq = fmaf(tu1[i][j], tu1[i][j], qq);
+      qq = fmaf(tu2[i][j], tu2[i][j], qq);
+      return cr[i] - qq;
+    };
+#pragma unroll
+    for (int i = 0; i < RC; ++i)
+#pragma unroll
+      for (int j = 0; j < J; ++j) e[i][j] = __builtin_amdgcn_exp2f(log_density(i, j));
+    {
+      float* dst = E + (s * kQ + q) * LL::kEB;
+#pragma unroll
+      for (int i = 0; i < RC; ++i)
+#pragma unroll
+        for (int j = 0; j < J; ++j) dst[i * J + j] = e[i][j];
+    }
+    wave_sync();
+    // phase 2: the denominator of Eq. Rik for each pixel of the chunk
+    const bool pv = p_r < nr;
+    float sm = 1.f;
+    if (pv) {
+      sm = E[p_e];
+#pragma unroll
+      for (int k = 1; k < kSlots; ++k) sm += E[k * kQ * LL::kEB + p_e];
+    }
+    const bool small = pv && sm < 0x1p-100f;
+    float inv = 0.f, lg = 0.f;
+    if (__builtin_amdgcn_ballot_w64(small) == 0) {
+      inv = __builtin_amdgcn_rcpf(sm);
+      lg = __builtin_amdgcn_logf(sm);
+    } else {
+      // A pixel whose nine densities all underflow is normalised with its
+      // largest log density subtracted first (the same posterior, Eq. Rik,
+      // without 0/0); every other pixel keeps its e.  The log densities
+      // replace e in LDS.
+      float* dst = E + (s * kQ + q) * LL::kEB;
+#pragma unroll
+      for (int i = 0; i < RC; ++i)
+#pragma unroll
+        for (int j = 0; j < J; ++j) dst[i * J + j] = log_density(i, j);
+      wave_sync();
+      if (pv) {
+        if (small) {
+          float m = E[p_e];
+#pragma unroll
+          for (int k = 1; k < kSlots; ++k) m = fmaxf(m, E[k * kQ * LL::kEB + p_e]);
+          float t = 0.f;
+#pragma unroll
+          for (int k = 0; k < kSlots; ++k) t += __builtin_amdgcn_exp2f(E[k * kQ * LL::kEB + p_e] - m);
+          inv = __builtin_amdgcn_rcpf(t);
+          lg = __builtin_amdgcn_logf(t) + m;
+          SH[p_e] = m;
+        } else {
+          inv = __builtin_amdgcn_rcpf(sm);
+          lg = __builtin_amdgcn_logf(sm);
+          SH[p_e] = INFINITY;  // not shifted
+        }
+      }
+      wave_sync();
+      const float* sh = SH + q * LL::kEB;
+#pragma unroll
+      for (int i = 0; i < RC; ++i)
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float m = sh[i * J + j];
+          if (m != INFINITY) e[i][j] = __builtin_amdgcn_exp2f(log_density(i, j) - m);
+        }
+    }
+    if (pv) {
+      INV[p_e] = inv;
+      // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
+      // integer-valued FP64 sums are exact, so L does not depend on how pixels
+      // are grouped into chunks and lanes
+      ll64 += rint((double)lg * 0x1p22);
+    }
+    wave_sync();
+    // phase 3: R = e / sum and the slot's sufficient statistics
+    {
+      const float* ivs = INV + q * LL::kEB;
+#pragma unroll
+      for (int i = 0; i < RC; ++i) {
+        const float rr = rrv[i];
+        const float r2 = vreg(rr * rr);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float R = e[i][j] * ivs[i * J + j];
+          Nj[j] += R;
+          Mj[j] = fmaf(rr, R, Mj[j]);
+          Qj[j] = fmaf(r2, R, Qj[j]);
+          const float rw = R * tw[i][j];
+          Sw += rw;
+          Sww = fmaf(rw, tw[i][j], Sww);
+          const float r1 = R * tu1[i][j];
+          Su1 += r1;
+          S11 = fmaf(r1, tu1[i][j], S11);
+          S12 = fmaf(r1, tu2[i][j], S12);
+          const float rb = R * tu2[i][j];
+          Su2 += rb;
+          S22 = fmaf(rb, tu2[i][j], S22);
+        }
+      }
+    }
+  }
+
+  // this lane's statistics of its slot over its columns: spatial moments
+  // about the cell origin from the per-column sums
+  float st[kStats];
+  st[S_N] = 0.f;
+  st[S_X] = 0.f;
+  st[S_Y] = 0.f;
+  st[S_XX] = 0.f;
+  st[S_XY] = 0.f;
+  st[S_YY] = 0.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const float c = (float)(q + kQ * j);
+    st[S_N] += Nj[j];
+    st[S_X] = fmaf(c, Nj[j], st[S_X]);
+    st[S_XX] = fmaf(c * c, Nj[j], st[S_XX]);
+    st[S_Y] += Mj[j];
+    st[S_XY] = fmaf(c, Mj[j], st[S_XY]);
+    st[S_YY] += Qj[j];
+  }
+  // colour moments in the whitened coordinates of the slot's record
+  st[S_L] = Sw;
+  st[S_A] = Su1;
+  st[S_B] = Su2;
+  st[S_LL] = Sww;
+  st[S_AA] = S11;
+  st[S_AB] = S12;
+  st[S_BB] = S22;
+  wave_sync();  // the last chunk's reads of E, INV and SH are done
+#pragma unroll
+  for (int t = 0; t < kStats; ++t) RED[lane * kStats + t] = st[t];
+  wave_sync();
+  // the cell's totals: the seven lanes of each slot in ascending phase order
+  float* part = reinterpret_cast<float*>(P.part) + ((size_t)sub * P.n_cell + cell) * kPartStride;
+  for (int o = lane; o < kSlots * kStats; o += 64) {
+    const int so = o / kStats, t = o - so * kStats;
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) a += RED[(so * kQ + k) * kStats + t];
+    part[o] = a;
+  }
+  // cell log-likelihood: ln 2 (sum of log2 terms) + pixels x ln(cmax); the
+  // integer-valued sums stay exact
+  double ll = ll64;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
+  const double cst = sub == 0 ? (double)(w * h) * Ip->lncmax : 0.0;
+  if (lane == 0) P.llp[(size_t)sub * P.n_cell + cell] = kLn2 * (ll * 0x1p-22) + cst;
+}
+
+// Columns per lane and rows per chunk for cells up to max_w wide: J = ceil(max_w / 7),
+// RC x max_w <= 64 (one lane per pixel in phases 0 and 2).  0 when the slot-lane
+// kernel does not cover this width.
+int slots_shape(int max_w, int* J, int* RC) {
+  if (max_w < 1 || max_w > 8 * kQ) return 0;
+  const int j = (max_w + kQ - 1) / kQ;
+  int rc;
+  switch (j) {
+    case 1: rc = 8; break;
+    case 2: rc = 4; break;
+    case 3: rc = 3; break;
+    case 4: rc = 2; break;
+    case 5: rc = max_w <= 32 ? 2 : 1; break;
+    default: rc = 1; break;
+  }
+  *J = j;
+  *RC = rc;
+  return 1;
+}
+
+namespace {
+template <int J, int RC>
+hipError_t launch_jrc(const DevPtrs& P, const float* lab, hipStream_t s) {
+  const dim3 grid((unsigned)(((size_t)P.n_cell * P.wpc + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (P.wpc == 4)
+    hipLaunchKernelGGL((k_slots<J, RC, 4>), grid, dim3(256), 0, s, P, lab);
+  else if (P.wpc == 2)
+    hipLaunchKernelGGL((k_slots<J, RC, 2>), grid, dim3(256), 0, s, P, lab);
+  else
+    hipLaunchKernelGGL((k_slots<J, RC, 1>), grid, dim3(256), 0, s, P, lab);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s) {
+  const int J = P.slot_j, RC = P.slot_rc;
+  if (J == 1 && RC == 8) return launch_jrc<1, 8>(P, lab, s);
+  if (J == 2 && RC == 4) return launch_jrc<2, 4>(P, lab, s);
+  if (J == 3 && RC == 3) return launch_jrc<3, 3>(P, lab, s);
+  if (J == 4 && RC == 2) return launch_jrc<4, 2>(P, lab, s);
+  if (J == 5 && RC == 2) return launch_jrc<5, 2>(P, lab, s);
+  if (J == 5 && RC == 1) return launch_jrc<5, 1>(P, lab, s);
+  if (J == 6 && RC == 1) return launch_jrc<6, 1>(P, lab, s);
+  if (J == 7 && RC == 1) return launch_jrc<7, 1>(P, lab, s);
+  if (J == 8 && RC == 1) return launch_jrc<8, 1>(P, lab, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gmmsp

@@ -184,6 +184,15 @@ class GMMSP:
         check(lib().gmmsp_get_schedule(self.handle, byref(w)))
         return w.value
 
+    def set_estep_kernel(self, kind: int):
+        """0: one pixel per lane; 1: one candidate slot per lane (cov_mode 0)."""
+        check(lib().gmmsp_set_estep_kernel(self.handle, int(kind)))
+
+    def get_estep_kernel(self) -> int:
+        k = c_int32()
+        check(lib().gmmsp_get_estep_kernel(self.handle, byref(k)))
+        return k.value
+
     def set_gather_lanes(self, lanes_per_superpixel: int):
         check(lib().gmmsp_set_gather_lanes(self.handle, int(lanes_per_superpixel)))
 
