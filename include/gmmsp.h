@@ -364,6 +364,23 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
                        int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
                        int32_t* counts_host, void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: serving loops, harnesses that forbid allocation).  The same as
+ * gmmsp_connectivity, with the workspace taken from a scratch array of
+ * GMMSP_CONN_STATIC_BYTES that the library keeps on each GPU it runs on until
+ * the process ends (its address is looked up on the first call on a device,
+ * with that device current).  The entry point allocates nothing: no hipMalloc,
+ * hipFree or host heap.  E_SIZE when the batch needs more than
+ * GMMSP_CONN_STATIC_BYTES (gmmsp_conn_workspace_bytes; about 88 bytes per
+ * pixel, so about 1.1 million pixels).  Every call on a GPU uses that GPU's
+ * one array and leaves its contents behind: calls that overlap on one GPU
+ * (several threads or streams) race, and the caller must serialise them.
+ * Synchronises `stream`. */
+#define GMMSP_CONN_STATIC_BYTES (96u << 20)
+int gmmsp_connectivity_static(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                              int32_t* out_dev, int32_t compact, int32_t* counts_host,
+                              void* stream);
+
 /* ------------------------------------------------------------------------
  * Accuracy measures of Sec. IV for each image of the batch: boundary recall
  * (BR), under-segmentation error (Eq. ue) and achievable segmentation

@@ -22,6 +22,7 @@ THETA_ROW_FULL = 21
 THETA_ROW_GRAY = 8
 THETA_ROWS = {0: THETA_ROW, 1: THETA_ROW3, 2: THETA_ROW_FULL, 3: THETA_ROW_GRAY}
 LL_CAP = 4096
+CONN_STATIC_BYTES = 96 << 20   # GMMSP_CONN_STATIC_BYTES
 
 
 class GmmspParams(ctypes.Structure):
@@ -89,6 +90,8 @@ _SIGS = {
                               c_size_t, c_void_p, c_void_p, c_void_p]),
     "gmmsp_connectivity": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                    c_int32, c_void_p, c_void_p]),
+    "gmmsp_connectivity_static": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                          c_void_p, c_void_p]),
     "gmmsp_last_error": (c_char_p, []),
 }
 

@@ -9,11 +9,16 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace gmmsp;
+
+// Device memory of the allocation-free connectivity entry point: each GPU the
+// library runs on holds one copy until the process ends.
+static __device__ __align__(256) unsigned char scratch[GMMSP_CONN_STATIC_BYTES];
 
 namespace {
 
@@ -1079,11 +1084,12 @@ int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
   return GMMSP_OK;
 }
 
-int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
-                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
-                       int32_t* counts_host, void* stream) {
-  if (!h || !lab_dev || !labels_dev || !out_dev || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
-  if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
+namespace {
+
+// The connectivity step on a given workspace; allocates nothing.
+int connectivity_run(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                     int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
+                     int32_t* counts_host, hipStream_t s) {
   if (h->n_pix >= ((int64_t)1 << 31) - 1)
     return fail(GMMSP_E_SIZE, "connectivity needs fewer than 2^31 - 1 pixels per batch");
   const ConnSizes z = conn_sizes(h);
@@ -1106,7 +1112,6 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
   C.colsum = (unsigned long long*)take(z.colsum);
   C.side = (int*)take(z.side);
   const int max_pix = z.max_pix, max_tiles = z.max_tiles;
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e = conn_launch_components(C, h->P.img, h->n_img, max_pix, max_tiles, labels_dev, s);
   int n_seg = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&n_seg, C.total, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1116,19 +1121,63 @@ int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* lab
   e = conn_launch_merge(C, h->P.img, h->n_img, max_pix, z.max_w, z.max_h, n_seg, lab_dev,
                         compact ? 1 : 0, out_dev, s);
   if (e == hipSuccess && counts_host) {
-    std::vector<int> c(4 * (size_t)h->n_img);
-    e = hipMemcpyAsync(c.data(), C.counts, sizeof(int) * c.size(), hipMemcpyDeviceToHost, s);
+    // segments, small, merged per image straight into the caller's array; the
+    // fourth entry (final segments) is formed here
+    e = hipMemcpyAsync(counts_host, C.counts, sizeof(int) * 4 * (size_t)h->n_img,
+                       hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess)
-      for (int32_t i = 0; i < h->n_img; ++i) {
-        counts_host[4 * i + 0] = c[4 * i + 0];
-        counts_host[4 * i + 1] = c[4 * i + 1];
-        counts_host[4 * i + 2] = c[4 * i + 2];
-        counts_host[4 * i + 3] = c[4 * i + 0] - c[4 * i + 2];
-      }
+      for (int32_t i = 0; i < h->n_img; ++i)
+        counts_host[4 * i + 3] = counts_host[4 * i + 0] - counts_host[4 * i + 2];
   }
   if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity");
   return GMMSP_OK;
+}
+
+// Scratch memory of gmmsp_connectivity_static: the address of this GPU's copy
+// of `scratch`, found once per device (host code never passes the array's
+// name itself, which is only a host-side stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+int gmmsp_connectivity(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                       int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
+                       int32_t* counts_host, void* stream) {
+  if (!h || !lab_dev || !labels_dev || !out_dev || !ws_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  if (((uintptr_t)ws_dev) & 255) return fail(GMMSP_E_INVAL, "workspace not 256-byte aligned");
+  return connectivity_run(h, lab_dev, labels_dev, out_dev, ws_dev, ws_bytes, compact, counts_host,
+                          (hipStream_t)stream);
+}
+
+int gmmsp_connectivity_static(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+                              int32_t* out_dev, int32_t compact, int32_t* counts_host,
+                              void* stream) {
+  if (!h || !lab_dev || !labels_dev || !out_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  const size_t need = conn_sizes(h).total;
+  if (need > (size_t)GMMSP_CONN_STATIC_BYTES)
+    return fail(GMMSP_E_SIZE, "connectivity needs %zu bytes of scratch, more than the %zu of the "
+                "allocation-free entry point", need, (size_t)GMMSP_CONN_STATIC_BYTES);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity_static: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMMSP_E_INVAL, "device %d out of range", dev);
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+      // once per device, with that device current: this GPU's copy of the array
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "gmmsp_connectivity_static: hipGetSymbolAddress");
+      if (!ptr) return fail(GMMSP_E_HIP, "gmmsp_connectivity_static: no scratch address");
+      g_scratch_dev[dev] = ptr;
+    }
+    ptr = g_scratch_dev[dev];
+  }
+  return connectivity_run(h, lab_dev, labels_dev, out_dev, ptr, GMMSP_CONN_STATIC_BYTES, compact,
+                          counts_host, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -358,6 +358,29 @@ class GMMSP:
                                        c_void_p(self._stream())))
         return out, counts
 
+    def conn_workspace_bytes(self) -> int:
+        nbytes = c_size_t(0)
+        check(lib().gmmsp_conn_workspace_bytes(self.handle, byref(nbytes)))
+        return nbytes.value
+
+    def connectivity_static(self, lab: torch.Tensor, labels: torch.Tensor,
+                            out: torch.Tensor | None = None, compact: bool = False):
+        """connectivity() on the library's own scratch array instead of a
+        workspace: the entry point for callers that cannot allocate (one array
+        per GPU, at most _lib.CONN_STATIC_BYTES of workspace; calls that
+        overlap on one GPU race)."""
+        if labels.dtype != torch.int32 or not labels.is_contiguous() or \
+                labels.numel() != self.n_pixels or labels.device != self.device:
+            raise ValueError("labels must be a contiguous int32 tensor of n_pixels on the handle's device")
+        if out is None:
+            out = torch.empty_like(labels)
+        counts = np.zeros((self.n_images, 4), dtype=np.int32)
+        check(lib().gmmsp_connectivity_static(self.handle, self._lab(lab, 3), c_void_p(_ptr(labels)),
+                                              c_void_p(_ptr(out)), 1 if compact else 0,
+                                              c_void_p(counts.ctypes.data),
+                                              c_void_p(self._stream())))
+        return out, counts
+
     # -- accuracy measures (Sec. IV: BR, Eq. ue, Eq. asa) ----------------------
     def metrics(self, labels: torch.Tensor, gt: torch.Tensor, n_gt, n_sp=None):
         """BR, UE, ASA per image of `labels` (int32, values in [0, n_sp[b]),
