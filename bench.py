@@ -70,9 +70,6 @@ def measured_traffic(pixel_evals_per_launch, kind: int):
     return round(t["bytes_per_pixel_eval"] * pixel_evals_per_launch, 0)
 
 
-WS_MASK = 0b0001111111   # warm-start outputs applied: the means and the spatial scales
-
-
 def load_or_train_weights(dev):
     """Weights trained by paper_1612_08792_amd.train_warmstart; trained here
     (outside the timed region) when the file is absent."""
@@ -234,7 +231,7 @@ def main():
         return it
 
     def step_warm():
-        warmstart.warm_start(m, lab, params, WS_MASK)
+        warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK)
         it = m.em_iterate(lab, args.cap, args.tol)
         m.label(lab, labels, want_ll=False)
         return it

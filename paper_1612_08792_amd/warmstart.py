@@ -19,6 +19,9 @@ from .gmmsp import GMMSP
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS_DIR = os.path.join(HERE, "weights")
 LAYERS = [(16, 32), (32, 32), (32, 32), (32, 10)]
+# outputs the trained network's theta^0 applies: the five mean offsets and the
+# two spatial log-scales (the colour variances stay at lambda^2)
+APPLY_MASK = 0b0001111111
 
 
 def init_params(seed: int = 0) -> np.ndarray:

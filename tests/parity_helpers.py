@@ -63,3 +63,29 @@ def oracle_margin(R: np.ndarray) -> np.ndarray:
 
 def oracle_slots(g, cand, values):
     return O.to_slots(g, cand, values).reshape(-1, 9)
+
+
+def window_step(g, z, cand, theta_t, k, R_gpu_window):
+    """Sampled parity on the window I_k (Eq. Ik) of superpixel k: the oracle's
+    E-step on the window's pixels at theta_t (Eq. Rik), compared with the GPU
+    posteriors of the same pixels in slot layout (R_gpu_window: (h, w, 9)), and
+    the oracle's M-step of k from it (Eqs. UpdateMu .. eigdecrc).  Returns (max
+    |R_gpu - R_oracle| on the window, the oracle's theta^{t+1} row of k, the
+    oracle posteriors and candidates of the window)."""
+    xb, xe, yb, ye = O.window(g, int(k))
+    zw, cw = z[yb:ye, xb:xe], cand[yb:ye, xb:xe]
+    Rw, _, _ = O.estep(zw, cw, theta_t)
+    # the oracle's posteriors by neighbour slot s = 3 (dy + 1) + (dx + 1)
+    sub = np.zeros((ye - yb, xe - xb, 9))
+    cx = (np.arange(xb, xe) // g.vx)[None, :, None]
+    cy = (np.arange(yb, ye) // g.vy)[:, None, None]
+    s = 3 * (cw // g.nx - cy + 1) + (cw % g.nx - cx + 1)
+    yy, xx, jj = np.nonzero(cw >= 0)
+    sub[yy, xx, s[yy, xx, jj]] = Rw[yy, xx, jj]
+    err = float(np.abs(R_gpu_window - sub).max())
+    pos = (cw == k).argmax(-1)
+    rk = np.take_along_axis(Rw, pos[..., None], -1).reshape(-1)
+    mu, sig, Nk = O.mstep_one(zw.reshape(-1, z.shape[-1]), rk, theta_t.mu[k], theta_t.sigma[k],
+                              O.Params())
+    row = O.theta_to_rows(O.Theta(mu[None], sig[None], np.array([Nk])))[0]
+    return err, row, Rw, cw

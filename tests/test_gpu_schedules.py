@@ -11,7 +11,7 @@ import torch
 import synth
 from oracle import gmm_oracle as O
 from paper_1612_08792_amd.gmmsp import GMMSP
-from parity_helpers import assert_theta_close, oracle_slots
+from parity_helpers import window_step, assert_theta_close, oracle_slots
 
 pytestmark = pytest.mark.gpu
 
@@ -167,3 +167,23 @@ def test_uneven_batch_of_64_images(dev):
         assert np.abs(R[m.image_slice(b)] - oracle_slots(g, cand, Ro)).max() <= 1e-5
         th1 = O.mstep(z, g, Ro, O.window_positions(g, cand), th, O.Params())
         assert_theta_close(th15[m.sp_slice(b)], O.theta_to_rows(th1), 1e-5, what=f"image {b}")
+    # one EM step on sampled windows of every image of the batch
+    rng = np.random.default_rng(64)
+    worst = 0.0
+    for b, im in enumerate(ims):
+        g = O.make_grid(im.W, im.H, K=im.K)
+        z = O.features(im.lab.cpu().numpy())
+        cand, _ = O.candidate_sets(g)
+        sl = m.sp_slice(b)
+        th = O.rows_to_theta(th14[sl])
+        Rimg = R[m.image_slice(b)].reshape(im.H, im.W, 9)
+        ks = rng.choice(g.K, 4, replace=False)
+        got, want = np.empty((4, 13)), np.empty((4, 13))
+        for j, k in enumerate(ks):
+            xb, xe, yb, ye = O.window(g, int(k))
+            err, want[j], _, _ = window_step(g, z, cand, th, k, Rimg[yb:ye, xb:xe])
+            worst = max(worst, err)
+            assert err <= 1e-5, (b, k, err)
+            got[j] = th15[sl][k]
+        assert_theta_close(got, want, 1e-5, what=f"image {b}, sampled windows")
+    say(f"64 images, 256 sampled windows: R err {worst:.2e}")
