@@ -161,6 +161,12 @@ def test_relative_tolerance_stop_matches_oracle(dev):
     assert abs(int(out["iters"][0]) - ref["iters"]) <= 1
     n = min(len(out["hist"]), len(ref["ll_hist"]))
     np.testing.assert_allclose(out["hist"][:n], ref["ll_hist"][:n], rtol=1e-6)
+    # The rule compares FP32-evaluated L values near the threshold, so the two
+    # runs may stop one pass apart; either way the GPU's final theta is the
+    # oracle's after as many M-steps.
+    t = int(out["iters"][0])
+    same = ref if ref["iters"] == t else O.run_em(im.lab.numpy(), g, max_iters=t)
+    assert_theta_close(out["theta"], O.theta_to_rows(same["theta"]), 1e-3, what=f"theta^{t}")
     say("stop rule iters gpu", out["iters"][0], "oracle", ref["iters"])
 
 
