@@ -231,7 +231,9 @@ def main():
         return it
 
     def step_warm():
-        warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK)
+        # the guarded start: two E-steps compare L(theta^0) of the network and
+        # of the grid seeds per image, timed as part of the step
+        warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK, guard=True)
         it = m.em_iterate(lab, args.cap, args.tol)
         m.label(lab, labels, want_ll=False)
         return it
@@ -261,6 +263,11 @@ def main():
         runs["plain"] = timed(step_plain, "plain")
     if args.mode in ("both", "warm"):
         runs["warm"] = timed(step_warm, "warm")
+    guard_fallbacks = None
+    if "warm" in runs:
+        flags = warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK, guard=True,
+                                     want_flags=True)
+        guard_fallbacks = int(flags.sum())
     main_run = runs["warm"] if "warm" in runs else runs["plain"]
     dt = main_run["dt"]
     fallback = 0
@@ -292,6 +299,7 @@ def main():
         compare["warm_vs_plain_final_L_rel"] = dict(mean=float(rel.mean()), min=float(rel.min()),
                                                     max=float(rel.max()))
         compare["fallback_images"] = fallback
+        compare["guard_seed_images"] = guard_fallbacks
         compare["speedup"] = round(compare["warm"]["mpix_per_s"] / compare["plain"]["mpix_per_s"], 4)
 
     out = {

@@ -307,6 +307,16 @@ int gmmsp_ws_forward(gmmsp_handle* h, const float* params_dev, int32_t b0, int32
  * iteration state: the handle is then initialised as by gmmsp_init_seeds. */
 int gmmsp_ws_apply(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask, void* stream);
 
+/* gmmsp_ws_apply with the grid seeds of Sec. III-C as the fallback, judged by
+ * the objective L(theta) of Sec. III-B (Eq. ftheta's log-likelihood): one
+ * E-step evaluates L(theta^0) for the grid seeds and one for the network's
+ * theta^0; every image whose network start has the lower L, or a non-finite
+ * one, starts from the grid seeds instead.  fallback_host (nullable,
+ * n_images int32): 1 where the seeds were kept; when given, `stream` is
+ * synchronised.  Costs two E-steps over the batch. */
+int gmmsp_ws_apply_guarded(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask,
+                           int32_t* fallback_host, void* stream);
+
 /* Training targets from the handle's current theta (for instance plain EM
  * after some passes): the inverse of the map above. */
 int gmmsp_ws_targets(gmmsp_handle* h, const float* lab_dev, void* stream);

@@ -78,6 +78,7 @@ _SIGS = {
     "gmmsp_ws_features": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmmsp_ws_forward": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "gmmsp_ws_apply": (c_int, [c_void_p, c_void_p, c_uint32, c_void_p]),
+    "gmmsp_ws_apply_guarded": (c_int, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "gmmsp_ws_targets": (c_int, [c_void_p, c_void_p, c_void_p]),
     "gmmsp_ws_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float,
                                     c_int32, c_int32, c_void_p, c_void_p]),

@@ -966,6 +966,34 @@ int gmmsp_ws_apply(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask, 
   return GMMSP_OK;
 }
 
+int gmmsp_ws_apply_guarded(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask,
+                           int32_t* fallback_host, void* stream) {
+  int rc = ws_check(h);
+  if (rc) return rc;
+  if (!lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  double* rows = h->P.part;  // staging, as in gmmsp_ws_apply
+  // L(theta^0) of the grid seeds, then of the network's theta^0 (one E-step
+  // each); images whose network start is worse, or not finite, are re-seeded
+  hipError_t e = launch_init_seeds(h->P, lab_dev, s);
+  if (e == hipSuccess) e = launch_ll_eval(h->P, lab_dev, 1, s);
+  if (e == hipSuccess) e = ws_launch_apply(h->P, lab_dev, h->ws.out, output_mask, rows, s);
+  if (e == hipSuccess) e = launch_set_params(h->P, rows, s);
+  if (e == hipSuccess) e = launch_ll_eval(h->P, lab_dev, 0, s);
+  if (e == hipSuccess) e = launch_seed_fallback(h->P, lab_dev, s);
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_apply_guarded");
+  h->initialised = true;
+  if (fallback_host) {
+    std::vector<ImgState> st(h->n_img);
+    e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_apply_guarded");
+    for (int32_t b = 0; b < h->n_img; ++b) fallback_host[b] = st[b].fallback;
+  }
+  return GMMSP_OK;
+}
+
 int gmmsp_ws_targets(gmmsp_handle* h, const float* lab_dev, void* stream) {
   int rc = ws_check(h);
   if (rc) return rc;

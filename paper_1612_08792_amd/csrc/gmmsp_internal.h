@@ -83,9 +83,10 @@ struct ImgState {           // 32 bytes
   int32_t t;                // passes evaluated since the last initialisation
   int32_t done;             // 1 once the stop rule held
   int32_t iters;            // M-steps applied
-  int32_t pad;
-  double ll_final;          // L(theta) of the last labelling pass
-  double pad2[2];
+  int32_t fallback;         // 1: the guarded warm start kept the grid seeds
+  double ll_final;          // L(theta) of the last labelling (or evaluation) pass
+  double ll_seed;           // L(theta^0) of the grid seeds (guarded warm start)
+  double pad;
 };
 
 struct CellDesc { int32_t img, cx, cy, pad; };
@@ -118,6 +119,12 @@ struct DevPtrs {
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s);
 hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s);
+// the grid seeds again for the images whose L(theta^0) (ll_final) is below that
+// of the seeds (ll_seed) or not finite; sets their fallback flag, clears it elsewhere
+hipError_t launch_seed_fallback(const DevPtrs& P, const float* lab, hipStream_t s);
+// L(theta) of the current theta per image into ll_final (to_seed = 0) or
+// ll_seed (to_seed = 1): one E-step, no M-step, no change of the EM state
+hipError_t launch_ll_eval(const DevPtrs& P, const float* lab, int to_seed, hipStream_t s);
 hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s);
 hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s);
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s);

@@ -162,12 +162,11 @@ __global__ __launch_bounds__(256) void k_reset_state(DevPtrs P) {
 }
 
 // Sec. III-C: mu_k = z_j at the seed pixel, Sigma_s = diag(v_x^2, v_y^2),
-// colour variances lambda^2.
-__global__ __launch_bounds__(256) void k_init_seeds(DevPtrs P, const float* __restrict__ lab) {
-  const int sp = blockIdx.x * 256 + threadIdx.x;
-  if (sp >= P.n_sp) return;
-  const SpDesc d = P.sp[sp];
-  const ImgDesc I = P.img[d.img];
+// colour variances lambda^2.  With `guarded`, only the images whose
+// L(theta^0) (ll_final) is below the seeds' (ll_seed) or not finite are
+// re-seeded, and every image's fallback flag records the choice.
+__device__ inline void seed_superpixel(DevPtrs& P, const float* __restrict__ lab, int sp,
+                                       const SpDesc& d, const ImgDesc& I) {
   const int x = d.kx * I.vx + I.vx / 2;
   const int y = d.ky * I.vy + I.vy / 2;
   const float* px = lab + 3 * (I.pix_off + (int64_t)y * I.W + x);
@@ -180,6 +179,21 @@ __global__ __launch_bounds__(256) void k_init_seeds(DevPtrs P, const float* __re
   q.det_ab = l2 * l2;
   store_theta_row(P.theta + (size_t)sp * kThetaRow, q, 0.0);
   write_records(P, I, d.kx, d.ky, q);
+}
+
+__global__ __launch_bounds__(256) void k_init_seeds(DevPtrs P, const float* __restrict__ lab,
+                                                    int guarded) {
+  const int sp = blockIdx.x * 256 + threadIdx.x;
+  if (sp >= P.n_sp) return;
+  const SpDesc d = P.sp[sp];
+  const ImgDesc I = P.img[d.img];
+  if (guarded) {
+    ImgState* st = P.state + d.img;
+    const bool keep = st->ll_final >= st->ll_seed;  // false for NaN
+    if (d.kx == 0 && d.ky == 0) st->fallback = keep ? 0 : 1;
+    if (keep) return;
+  }
+  seed_superpixel(P, lab, sp, d, I);
 }
 
 __global__ __launch_bounds__(256) void k_set_params(DevPtrs P, const double* __restrict__ rows) {
@@ -553,6 +567,8 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
 // ---------------------------------------------------------------------------
 constexpr int kLLThreads = 1024;
 
+// final_pass: 0 the EM pass (history, stop rule), 1 L into ll_final, 2 L
+// into ll_seed (the last two change no EM state)
 __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
                                                           int nsub) {
   __shared__ double red[kLLThreads];
@@ -578,6 +594,10 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_
   }
   if (threadIdx.x != 0) return;
   const double L = red[0];
+  if (final_pass == 2) {
+    st->ll_seed = L;
+    return;
+  }
   if (final_pass) {
     st->ll_final = L;
     return;
@@ -782,7 +802,24 @@ hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s) {
 
 hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s) {
   if (P.cov_mode) return launch_alt_init_seeds(P, lab, s);
-  hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab);
+  hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_fallback(const DevPtrs& P, const float* lab, hipStream_t s) {
+  if (P.cov_mode) return hipErrorInvalidValue;  // the warm start serves cov_mode 0
+  hipLaunchKernelGGL(k_init_seeds, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P, lab, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ll_eval(const DevPtrs& P, const float* lab, int to_seed, hipStream_t s) {
+  // the statistics pass evaluates L(theta) per cell wave (its partials are
+  // scratch until the next pass); images marked done are evaluated too
+  hipError_t e = launch_reset_state(P, s);
+  if (e == hipSuccess) e = launch_estep_stats(P, lab, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, to_seed ? 2 : 1,
+                     P.wpc);
   return hipGetLastError();
 }
 

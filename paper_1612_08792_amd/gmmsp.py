@@ -296,6 +296,17 @@ class GMMSP:
         check(lib().gmmsp_ws_apply(self.handle, self._lab(lab), int(mask),
                                    c_void_p(self._stream())))
 
+    def ws_apply_guarded(self, lab: torch.Tensor, mask: int = _lib.WS_ALL_OUTPUTS,
+                         want_flags: bool = False):
+        """ws_apply, keeping the grid seeds for every image whose L(theta^0)
+        under the network is lower (or not finite).  With want_flags, returns
+        the per-image fallback flags (synchronises)."""
+        flags = np.zeros(self.n_images, dtype=np.int32) if want_flags else None
+        check(lib().gmmsp_ws_apply_guarded(self.handle, self._lab(lab), int(mask),
+                                           c_void_p(flags.ctypes.data) if want_flags else None,
+                                           c_void_p(self._stream())))
+        return flags
+
     def ws_targets(self, lab: torch.Tensor):
         check(lib().gmmsp_ws_targets(self.handle, self._lab(lab), c_void_p(self._stream())))
 

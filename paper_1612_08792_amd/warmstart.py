@@ -93,12 +93,17 @@ def train(images, device="cuda", epochs: int = 30, batch_images: int = 64, lr: f
 
 
 def warm_start(m: GMMSP, lab: torch.Tensor, params: torch.Tensor,
-               mask: int = _lib.WS_ALL_OUTPUTS):
-    """theta^0 of every image of the handle from the network."""
+               mask: int = _lib.WS_ALL_OUTPUTS, guard: bool = False, want_flags: bool = False):
+    """theta^0 of every image of the handle from the network.  With guard, an
+    image whose L(theta^0) would be lower than with the grid seeds keeps the
+    seeds (returns the per-image flags when want_flags)."""
     m.ws_attach()
     m.ws_features(lab)
     m.ws_forward(params)
+    if guard:
+        return m.ws_apply_guarded(lab, mask, want_flags)
     m.ws_apply(lab, mask)
+    return None
 
 
 def save(params: torch.Tensor, path: str, info: dict):

@@ -4,7 +4,8 @@ Two images of the 4K batch workload (3840x2160 Voronoi-Lab, 2000 regions, noise
 sigma ~ U[1, 6], K = 10000 requested -> v = 28, 137 x 77 = 10549 superpixels)
 run exactly the benchmark's step in its launch configuration: the library's
 schedule autotuners, the learned warm start with the benchmark's output mask
-(features, network, theta^0), EM until the relative change of L is <= 1e-5
+(features, network, theta^0, and the guard that keeps the grid seeds where
+they give the higher L(theta^0)), EM until the relative change of L is <= 1e-5
 (cap 200; Algorithm 1 with the stop rule), and the labels (Eq. obtLi).  Checked:
 
 * theta^0 from the network's outputs against the oracle's map (ws_oracle) with
@@ -52,7 +53,8 @@ def run(dev):
     m = GMMSP([(im.W, im.H) for im in ims], K=ims[0].K, device=dev)
     m.autotune(lab, passes=3, cache=None)
     params = warmstart.load(train_warmstart.DEFAULT_OUT, dev)
-    warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK)
+    flags = warmstart.warm_start(m, lab, params, warmstart.APPLY_MASK, guard=True,
+                                 want_flags=True)
     theta0 = m.get_params()
     out = m.ws_read("out")
     iters = m.em_iterate(lab, 200, 1e-5)
@@ -65,7 +67,7 @@ def run(dev):
     theta_f1 = m.get_params()
     say(f"passes {list(iters)}, schedule: kernel {m.get_estep_kernel()}, "
         f"{m.get_schedule()} waves per cell, {m.get_gather_lanes()} gather lanes")
-    return dict(ims=ims, m=m, theta0=theta0, out=out, iters=iters, labels=labels,
+    return dict(ims=ims, m=m, flags=flags, theta0=theta0, out=out, iters=iters, labels=labels,
                 theta_f=theta_f, theta_f1=theta_f1, R=R)
 
 
@@ -75,6 +77,11 @@ def test_warm_start_theta0_matches_oracle(run):
         g = m.grids[b]
         assert (g.vx, g.vy, g.nx, g.ny) == (28, 28, 137, 77)
         sl = m.sp_slice(b)
+        if run["flags"][b]:   # the guard kept the grid seeds for this image
+            og = O.make_grid(im.W, im.H, K=im.K)
+            seeds = O.theta_to_rows(O.init_theta(og, O.features(im.lab.numpy()), O.Params()))
+            np.testing.assert_array_equal(run["theta0"][sl, :12], seeds[:, :12])
+            continue
         want = WS.theta0_rows(run["out"][sl].reshape(g.ny, g.nx, 16)[..., :10], im.lab.numpy(),
                               g.vx, g.vy, 8.0, warmstart.APPLY_MASK)
         want[:, 5] = np.maximum(want[:, 5], 2.0)

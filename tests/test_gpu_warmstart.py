@@ -206,6 +206,38 @@ def test_non_finite_outputs_fall_back_to_grid_init(batch, dev):
         np.testing.assert_array_equal(rows[m.sp_slice(b), :12], O.theta_to_rows(th)[:, :12])
 
 
+def test_guarded_warm_start_keeps_the_better_start(batch, dev):
+    """gmmsp_ws_apply_guarded: per image, the start with the higher L(theta^0)
+    (the oracle's L of the grid seeds and of the network's theta^0 decides
+    wherever the two differ clearly), and exactly that start's theta^0; weights
+    scaled up 40-fold put every mean far off, and every image keeps the seeds."""
+    from paper_1612_08792_amd import train_warmstart
+    ims, lab, m = batch
+    trained = warmstart.load(train_warmstart.DEFAULT_OUT, dev)
+    for name, params in (("trained", trained), ("corrupted", trained * 40.0)):
+        m.ws_forward(params)
+        m.ws_apply(lab, warmstart.APPLY_MASK)            # the network's theta^0, unguarded
+        warm_rows = m.get_params()
+        flags = m.ws_apply_guarded(lab, warmstart.APPLY_MASK, want_flags=True)
+        rows = m.get_params()
+        for b, im in enumerate(ims):
+            sl = m.sp_slice(b)
+            g = O.make_grid(im.W, im.H, K=im.K)
+            z = O.features(im.lab.numpy())
+            cand, _ = O.candidate_sets(g)
+            seeds = O.theta_to_rows(O.init_theta(g, z, O.Params()))
+            L_seed = O.estep(z, cand, O.rows_to_theta(seeds))[2]
+            L_warm = O.estep(z, cand, O.rows_to_theta(warm_rows[sl]))[2]
+            say(f"{name} image {b}: L(seeds) {L_seed:.6e} L(network) {L_warm:.6e} "
+                f"fallback {flags[b]}")
+            if abs(L_warm - L_seed) > 1e-6 * abs(L_seed):
+                assert flags[b] == int(L_warm < L_seed)
+            want = seeds if flags[b] else warm_rows[sl]
+            np.testing.assert_array_equal(rows[sl, :12], want[:, :12])
+        if name == "corrupted":
+            assert flags.tolist() == [1] * len(ims)
+
+
 def test_training_lowers_loss_and_warm_start_gains(dev):
     say("warm start: train on 512 images, evaluate 32 held out")
     train_ims = [synth.config4_image(10000 + i, dev) for i in range(512)]
@@ -220,7 +252,7 @@ def test_training_lowers_loss_and_warm_start_gains(dev):
     plain.init_seeds(lab)
     plain.em_iterate(lab, 150, 1e-5)
     warm = GMMSP(sizes, K=400, device=dev)
-    warmstart.warm_start(warm, lab, params, 0b0001111111)
+    warmstart.warm_start(warm, lab, params, warmstart.APPLY_MASK)
     warm.em_iterate(lab, 150, 1e-5)
     tp, tw, dl = [], [], []
     for b in range(len(test_ims)):
