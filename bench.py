@@ -214,11 +214,12 @@ def main():
     m = GMMSP(sizes, K=K_req, device=dev)
     labels = torch.empty(m.n_pixels, dtype=torch.int32, device=dev)
     n_pix = m.n_pixels
-    # schedules (waves per cell, lanes per superpixel of the gather) timed on
-    # this batch by the library's autotuners, outside the timed region
-    wpc = m.autotune(lab, passes=3, cache=None)
-    log(f"autotuned: {wpc} waves per cell, {m.get_gather_lanes()} gather lanes "
-        f"(E-step ms {m.tune_ms}, gather ms {m.tune_gather_ms})")
+    # schedules (statistics-pass kind, rows per chunk, waves per cell, lanes per
+    # superpixel of the gather) timed on this batch by the library's
+    # autotuners, outside the timed region
+    m.autotune(lab, passes=3, cache=None)
+    log(f"autotuned: {m.schedule()} (statistics pass ms {m.tune_ms}, "
+        f"gather ms {m.tune_gather_ms})")
     params = None
     if args.mode in ("both", "warm"):
         params = load_or_train_weights(dev)
@@ -328,8 +329,7 @@ def main():
             "passes_max": int(iters.max()),
             "estep_mpix_per_s_per_pass": round(per_iter_mpix, 1),
             "plain_vs_warm": compare,
-            "schedule": {"estep_kernel": kind, "waves_per_cell": m.get_schedule(),
-                         "gather_lanes": m.get_gather_lanes()},
+            "schedule": m.schedule(),
         },
         "roofline": {
             "bound": "alu",

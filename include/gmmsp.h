@@ -200,12 +200,41 @@ int gmmsp_get_schedule(const gmmsp_handle* h, int32_t* waves_per_cell);
 int gmmsp_set_estep_kernel(gmmsp_handle* h, int32_t kind);
 int gmmsp_get_estep_kernel(const gmmsp_handle* h, int32_t* kind);
 
-/* Autotuner: times `passes` statistics passes (after three untimed passes)
- * from the grid initialisation for each schedule 1, 2, 4 with HIP events on
- * `stream`; a schedule with more waves is kept only if it is more than 3 %
- * faster than the best with fewer.  Leaves the handle initialised by
- * gmmsp_init_seeds.  ms_host (nullable, 3 doubles): the measured times (-1
- * for a schedule not timed; with cov_mode 1, 2 or 3 only schedule 1 is). */
+/* Tile height of the slot-lane pass (kind 1): the cell rows each chunk takes
+ * (every lane evaluates rows x J pixels of its slot per chunk, J = ceil(v_x /
+ * 7) columns).  Built values: J = 1: 8, 4, 2; J = 2: 4, 2, 1; J = 3: 3, 2, 1;
+ * J = 4 and J = 5 (v_x <= 32): 2, 1; otherwise 1.  The default is the
+ * largest.  E_INVAL for a value not built for this batch's widest cell, or
+ * when the batch has no slot-lane pass.  With one wave per cell every value
+ * gives the same result bit for bit (the per-pixel arithmetic and the order of
+ * every sum are the same); with more, the value decides which rows each wave
+ * takes, so the FP32 sums group differently.  get returns 0 without a
+ * slot-lane pass. */
+int gmmsp_set_slot_rows(gmmsp_handle* h, int32_t rows);
+int gmmsp_get_slot_rows(const gmmsp_handle* h, int32_t* rows);
+
+/* Log-likelihood fusion (Algorithm 1's stop rule): with on = 1 (default) the
+ * slot-lane pass also forms L(theta^t) per image -- the image's last cell wave
+ * to finish adds the per-wave terms in a fixed order -- and applies the stop
+ * rule, so an em pass is two launches (statistics, gather); with 0, or with
+ * the pixel-lane pass, a separate reduction kernel does it (its sums are
+ * grouped differently).  get reports whether fusion is in effect. */
+int gmmsp_set_ll_fusion(gmmsp_handle* h, int32_t on);
+int gmmsp_get_ll_fusion(const gmmsp_handle* h, int32_t* on);
+
+/* Autotuner of the statistics pass: for each candidate schedule, `passes`
+ * statistics passes with L(theta^t) (after three untimed) from the grid
+ * initialisation, timed with HIP events on `stream`.  Candidates, in order of
+ * preference: the slot-lane pass (kind 1) with each built rows-per-chunk value,
+ * largest first, then the pixel-lane pass (kind 0); 1, 2 and 4 waves per cell
+ * each.  A later candidate is kept only if it is more than 3 % faster than the
+ * best before it.  Sets the kind, rows per chunk and waves per cell; leaves the
+ * handle initialised by gmmsp_init_seeds; *chosen = the waves per cell.
+ * ms_host (nullable, GMMSP_TUNE_CANDIDATES doubles): the time of candidate
+ * 3 v + w, v = 0, 1, 2 the slot-lane pass with the v-th rows value, v = 3 the
+ * pixel-lane pass, w = 0, 1, 2 for 1, 2, 4 waves per cell; -1 where not timed
+ * (with cov_mode 1, 2 or 3 only entry 9, one wave per cell, is). */
+#define GMMSP_TUNE_CANDIDATES 12
 int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double* ms_host,
                    int32_t* chosen, void* stream);
 

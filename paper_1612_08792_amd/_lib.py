@@ -23,6 +23,7 @@ THETA_ROW_GRAY = 8
 THETA_ROWS = {0: THETA_ROW, 1: THETA_ROW3, 2: THETA_ROW_FULL, 3: THETA_ROW_GRAY}
 LL_CAP = 4096
 CONN_STATIC_BYTES = 96 << 20   # GMMSP_CONN_STATIC_BYTES
+TUNE_CANDIDATES = 12           # GMMSP_TUNE_CANDIDATES
 
 
 class GmmspParams(ctypes.Structure):
@@ -64,6 +65,10 @@ _SIGS = {
     "gmmsp_get_schedule": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_set_estep_kernel": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_estep_kernel": (c_int, [c_void_p, POINTER(c_int32)]),
+    "gmmsp_set_slot_rows": (c_int, [c_void_p, c_int32]),
+    "gmmsp_get_slot_rows": (c_int, [c_void_p, POINTER(c_int32)]),
+    "gmmsp_set_ll_fusion": (c_int, [c_void_p, c_int32]),
+    "gmmsp_get_ll_fusion": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_autotune": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32), c_void_p]),
     "gmmsp_set_gather_lanes": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_gather_lanes": (c_int, [c_void_p, POINTER(c_int32)]),

@@ -204,7 +204,7 @@ struct gmmsp_handle {
   hipGraphExec_t gexec = nullptr;
   const float* g_lab = nullptr;
   double g_tol = 0.0;
-  int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1;
+  int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1, g_rc = 0, g_fuse = -1;
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -308,6 +308,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   for (const ImgDesc& d : descs) max_vx = std::max(max_vx, d.vx);
   P.estep = 0;
   if (P.cov_mode == 0 && slots_shape(max_vx, &P.slot_j, &P.slot_rc)) P.estep = 1;
+  P.fuse_ll = 1;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -403,6 +404,22 @@ int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
 
 namespace {
 
+// One em pass (Algorithm 1): the statistics pass with L(theta^t) and the stop
+// rule, then the M-step gather.  a and b (nullable) bracket the statistics
+// pass with events.
+hipError_t em_pass(const DevPtrs& P, const float* lab, double rel_tol, hipStream_t s, hipEvent_t a,
+                   hipEvent_t b) {
+  const bool fused = ll_fused(P);
+  hipError_t e = hipSuccess;
+  if (a) e = hipEventRecord(a, s);
+  if (e == hipSuccess)
+    e = fused ? launch_estep_ll(P, lab, LL_EM, rel_tol, s) : launch_estep_stats(P, lab, s);
+  if (e == hipSuccess && b) e = hipEventRecord(b, s);
+  if (e == hipSuccess && !fused) e = launch_ll_update(P, rel_tol, s);
+  if (e == hipSuccess) e = launch_finalize(P, s);
+  return e;
+}
+
 // Capture `len` em passes into a graph on the handle's private stream.
 int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t len) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
@@ -410,11 +427,8 @@ int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t le
   h->gexec = nullptr;
   h->graph = nullptr;
   hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
-  for (int32_t i = 0; i < len && e == hipSuccess; ++i) {
-    e = launch_estep_stats(h->P, lab, h->gstream);
-    if (e == hipSuccess) e = launch_ll_update(h->P, rel_tol, h->gstream);
-    if (e == hipSuccess) e = launch_finalize(h->P, h->gstream);
-  }
+  for (int32_t i = 0; i < len && e == hipSuccess; ++i)
+    e = em_pass(h->P, lab, rel_tol, h->gstream, nullptr, nullptr);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(h->gstream, &g);
   if (e == hipSuccess) e = e2;
@@ -430,6 +444,8 @@ int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t le
   h->g_wpc = h->P.wpc;
   h->g_glanes = h->P.glanes;
   h->g_estep = h->P.estep;
+  h->g_rc = h->P.slot_rc;
+  h->g_fuse = h->P.fuse_ll;
   return GMMSP_OK;
 }
 
@@ -445,7 +461,8 @@ int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, doubl
   const int32_t G = h->graph_passes;
   // the graph holds the kernels and arguments of the schedule it was captured with
   if (!h->gexec || h->g_lab != lab || h->g_tol != rel_tol || h->g_len != G || h->g_wpc != h->P.wpc ||
-      h->g_glanes != h->P.glanes || h->g_estep != h->P.estep) {
+      h->g_glanes != h->P.glanes || h->g_estep != h->P.estep || h->g_rc != h->P.slot_rc ||
+      h->g_fuse != h->P.fuse_ll) {
     int rc = capture_passes(h, lab, rel_tol, G);
     if (rc) return rc;
   }
@@ -513,11 +530,8 @@ int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, d
     launched = it;
   }
   for (; it < max_iters && !all_done; ++it) {
-    if (h->profile) e = hipEventRecord(h->ev[2 * it], s);
-    if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
-    if (e == hipSuccess && h->profile) e = hipEventRecord(h->ev[2 * it + 1], s);
-    if (e == hipSuccess) e = launch_ll_update(h->P, rel_tol, s);
-    if (e == hipSuccess) e = launch_finalize(h->P, s);
+    e = em_pass(h->P, lab_dev, rel_tol, s, h->profile ? h->ev[2 * it] : nullptr,
+                h->profile ? h->ev[2 * it + 1] : nullptr);
     if (e != hipSuccess) return hip_fail(e, "em pass");
     ++launched;
     if (rel_tol > 0.0) {
@@ -645,6 +659,41 @@ int gmmsp_get_estep_kernel(const gmmsp_handle* h, int32_t* kind) {
   return GMMSP_OK;
 }
 
+int gmmsp_set_slot_rows(gmmsp_handle* h, int32_t rows) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (!h->P.slot_j) return fail(GMMSP_E_INVAL, "this batch has no slot-lane pass");
+  int32_t max_vx = 0;
+  for (const ImgDesc& d : h->img) max_vx = std::max(max_vx, d.vx);
+  int J = 0, max_rc = 0, built[3] = {0, 0, 0};
+  (void)slots_shape(max_vx, &J, &max_rc);
+  const int n = slots_rows(J, max_rc, built, 3);
+  for (int i = 0; i < n; ++i)
+    if (built[i] == rows) {
+      h->P.slot_rc = rows;
+      return GMMSP_OK;
+    }
+  return fail(GMMSP_E_INVAL, "%d rows per chunk is not built for cells %d pixels wide", rows, max_vx);
+}
+
+int gmmsp_get_slot_rows(const gmmsp_handle* h, int32_t* rows) {
+  if (!h || !rows) return fail(GMMSP_E_INVAL, "null pointer");
+  *rows = h->P.slot_j ? h->P.slot_rc : 0;
+  return GMMSP_OK;
+}
+
+int gmmsp_set_ll_fusion(gmmsp_handle* h, int32_t on) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (on != 0 && on != 1) return fail(GMMSP_E_INVAL, "fusion flag must be 0 or 1");
+  h->P.fuse_ll = on;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_ll_fusion(const gmmsp_handle* h, int32_t* on) {
+  if (!h || !on) return fail(GMMSP_E_INVAL, "null pointer");
+  *on = ll_fused(h->P) ? 1 : 0;
+  return GMMSP_OK;
+}
+
 int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (lanes_per_superpixel != 1 && lanes_per_superpixel != 4 && lanes_per_superpixel != 16)
@@ -679,48 +728,70 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
-  const int32_t cand[3] = {1, 2, 4};
-  const int n_cand = h->P.cov_mode != 0 ? 1 : 3;  // the other covariance models have one schedule
+  // candidates in order of preference: the slot-lane pass with each rows-per-
+  // chunk value (largest first), then the pixel-lane pass; 1, 2, 4 waves per
+  // cell each.  Index 3 v + w, v = 0..2 the rows values, v = 3 the pixel-lane
+  // pass, w = 0..2 the waves per cell.
+  struct Cand { int32_t kind, rc, wpc, idx; };
+  std::vector<Cand> cands;
+  const int32_t wpcs[3] = {1, 2, 4};
+  if (h->P.cov_mode != 0) {
+    cands.push_back({0, 0, 1, 9});  // the other covariance models have one schedule
+  } else {
+    int max_j = 0, max_rc = 0;
+    int rows[3] = {0, 0, 0};
+    int n_rows = 0;
+    int32_t max_vx = 0;
+    for (const ImgDesc& d : h->img) max_vx = std::max(max_vx, d.vx);
+    if (slots_shape(max_vx, &max_j, &max_rc)) n_rows = slots_rows(max_j, max_rc, rows, 3);
+    for (int v = 0; v < n_rows; ++v)
+      for (int w = 0; w < 3; ++w) cands.push_back({1, rows[v], wpcs[w], 3 * v + w});
+    for (int w = 0; w < 3; ++w) cands.push_back({0, h->P.slot_rc, wpcs[w], 9 + w});
+  }
   if (ms_host)
-    for (int c = 0; c < 3; ++c) ms_host[c] = -1.0;
+    for (int c = 0; c < GMMSP_TUNE_CANDIDATES; ++c) ms_host[c] = -1.0;
   double best = 0.0;
-  int32_t pick = 1;
+  Cand pick = cands[0];
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  for (int c = 0; c < n_cand && e == hipSuccess; ++c) {
-    h->P.wpc = cand[c];
+  for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+    h->P.estep = cands[c].kind;
+    if (h->P.slot_j) h->P.slot_rc = cands[c].rc;
+    h->P.wpc = cands[c].wpc;
     e = launch_reset_state(h->P, s);
     if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
     double tot = 0.0;
     // kTuneWarm untimed passes (the first passes from the grid seeds run
-    // slower than later ones), then `passes` timed ones
+    // slower than later ones), then `passes` timed ones: the statistics pass
+    // with L(theta^t) and the stop rule (one launch where they are fused)
     for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
       e = hipEventRecord(a, s);
-      if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
+      if (e == hipSuccess) e = launch_estep_ll(h->P, lab_dev, LL_EM, 0.0, s);
       if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = launch_ll_update(h->P, 0.0, s);
       if (e == hipSuccess) e = launch_finalize(h->P, s);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       if (i >= kTuneWarm) tot += ms;
     }
-    if (ms_host) ms_host[c] = tot;
+    if (ms_host) ms_host[cands[c].idx] = tot;
     if (c == 0 || tot < kTuneMargin * best) {
       best = tot;
-      pick = cand[c];
+      pick = cands[c];
     }
   }
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
-  h->P.wpc = pick;
+  h->P.estep = pick.kind;
+  if (h->P.slot_j) h->P.slot_rc = pick.rc;
+  h->P.wpc = pick.wpc;
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
   if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune");
   h->initialised = true;
-  *chosen = pick;
+  *chosen = pick.wpc;
   return GMMSP_OK;
 }
 

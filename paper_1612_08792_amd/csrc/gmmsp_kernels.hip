@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void k_reset_state(DevPtrs P) {
   st->done = 0;
   st->iters = 0;
   st->ll_final = 0.0;
+  st->arrive = 0;
 }
 
 // Sec. III-C: mu_k = z_j at the seed pixel, Sigma_s = diag(v_x^2, v_y^2),
@@ -567,8 +568,8 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
 // ---------------------------------------------------------------------------
 constexpr int kLLThreads = 1024;
 
-// final_pass: 0 the EM pass (history, stop rule), 1 L into ll_final, 2 L
-// into ll_seed (the last two change no EM state)
+// final_pass: LL_EM the EM pass (history, stop rule), LL_FINAL L into
+// ll_final, LL_SEED L into ll_seed (the last two change no EM state)
 __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
                                                           int nsub) {
   __shared__ double red[kLLThreads];
@@ -592,31 +593,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  const double L = red[0];
-  if (final_pass == 2) {
-    st->ll_seed = L;
-    return;
-  }
-  if (final_pass) {
-    st->ll_final = L;
-    return;
-  }
-  const int t = st->t;
-  double* hist = P.ll_hist + (size_t)b * kLLCap;
-  if (t < kLLCap) hist[t] = L;
-  bool conv = false;
-  if (rel_tol > 0.0 && t >= 1) {
-    const double Lp = hist[t - 1];
-    conv = fabs(L - Lp) <= rel_tol * fabs(Lp);
-  }
-  if (conv) {
-    st->done = 1;
-    atomicAdd(P.n_done, 1);
-  } else {
-    st->iters = t + 1;
-  }
-  st->t = t + 1;
+  if (threadIdx.x == 0) ll_commit(P, b, red[0], final_pass, rel_tol);
 }
 
 // ---------------------------------------------------------------------------
@@ -816,11 +793,8 @@ hipError_t launch_ll_eval(const DevPtrs& P, const float* lab, int to_seed, hipSt
   // the statistics pass evaluates L(theta) per cell wave (its partials are
   // scratch until the next pass); images marked done are evaluated too
   hipError_t e = launch_reset_state(P, s);
-  if (e == hipSuccess) e = launch_estep_stats(P, lab, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, to_seed ? 2 : 1,
-                     P.wpc);
-  return hipGetLastError();
+  if (e == hipSuccess) e = launch_estep_ll(P, lab, to_seed ? LL_SEED : LL_FINAL, 0.0, s);
+  return e;
 }
 
 hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s) {
@@ -831,7 +805,7 @@ hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
   if (P.cov_mode) return launch_alt_cells(P, 0, lab, nullptr, nullptr, s);
-  if (P.estep == 1) return launch_estep_slots(P, lab, s);
+  if (P.estep == 1) return launch_estep_slots(P, lab, LL_NONE, 0.0, s);
   const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
   if (P.wpc == 4)
     hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
@@ -846,7 +820,17 @@ hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s)
 }
 
 hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, rel_tol, 0, P.wpc);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, rel_tol, (int)LL_EM,
+                     P.wpc);
+  return hipGetLastError();
+}
+
+hipError_t launch_estep_ll(const DevPtrs& P, const float* lab, int mode, double rel_tol,
+                           hipStream_t s) {
+  if (ll_fused(P)) return launch_estep_slots(P, lab, mode, rel_tol, s);
+  hipError_t e = launch_estep_stats(P, lab, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, rel_tol, mode, P.wpc);
   return hipGetLastError();
 }
 
@@ -869,7 +853,7 @@ hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hip
     hipLaunchKernelGGL(k_cells<M_LABEL>, dim3(blocks_for(P.n_cell, kWavesPerBlock)), dim3(256), 0,
                        s, P, lab, labels, (float*)nullptr);
   }
-  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, 1, 1);
+  hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, (int)LL_FINAL, 1);
   return hipGetLastError();
 }
 

@@ -193,6 +193,32 @@ class GMMSP:
         check(lib().gmmsp_get_estep_kernel(self.handle, byref(k)))
         return k.value
 
+    def set_slot_rows(self, rows: int):
+        """Rows per chunk (tile height) of the slot-lane pass."""
+        check(lib().gmmsp_set_slot_rows(self.handle, int(rows)))
+
+    def get_slot_rows(self) -> int:
+        r = c_int32()
+        check(lib().gmmsp_get_slot_rows(self.handle, byref(r)))
+        return r.value
+
+    def set_ll_fusion(self, on: bool):
+        """L(theta^t) and the stop rule inside the slot-lane pass (1) or in a
+        reduction kernel of their own (0)."""
+        check(lib().gmmsp_set_ll_fusion(self.handle, int(bool(on))))
+
+    def get_ll_fusion(self) -> int:
+        r = c_int32()
+        check(lib().gmmsp_get_ll_fusion(self.handle, byref(r)))
+        return r.value
+
+    def schedule(self) -> dict:
+        """The schedule in effect: statistics-pass kind, rows per chunk, waves
+        per cell, gather lanes, L fusion."""
+        return {"estep_kernel": self.get_estep_kernel(), "rows_per_chunk": self.get_slot_rows(),
+                "waves_per_cell": self.get_schedule(), "gather_lanes": self.get_gather_lanes(),
+                "ll_fused": self.get_ll_fusion()}
+
     def set_gather_lanes(self, lanes_per_superpixel: int):
         check(lib().gmmsp_set_gather_lanes(self.handle, int(lanes_per_superpixel)))
 
@@ -212,12 +238,12 @@ class GMMSP:
                 hashlib.sha256(grids.encode()).hexdigest()[:16])
 
     def autotune(self, lab: torch.Tensor, passes: int = 3, cache: str | None = "default") -> int:
-        """Pick the waves-per-cell schedule of the statistics pass, then the
-        lanes per superpixel of the gather, by timing them on this batch
-        (native loops in the library); results are cached by batch geometry in
-        a JSON file (~/.cache/gmmsp/schedules.json unless another path or None
-        is given).  Returns the waves per cell.  Leaves the handle initialised
-        by init_seeds."""
+        """Pick the statistics-pass schedule (kind, rows per chunk, waves per
+        cell), then the lanes per superpixel of the gather, by timing them on
+        this batch (native loops in the library); results are cached by batch
+        geometry in a JSON file (~/.cache/gmmsp/schedules.json unless another
+        path or None is given).  Returns the waves per cell.  Leaves the handle
+        initialised by init_seeds."""
         import json
         import os
         path = None
@@ -233,16 +259,24 @@ class GMMSP:
                     table = json.load(f)
             except (OSError, ValueError):
                 table = {}
-        if key in table:
-            self.set_schedule(int(table[key]["waves_per_cell"]))
-            self.set_gather_lanes(int(table[key].get("lanes_per_superpixel", 1)))
+        entry = table.get(key)
+        if entry and "estep_kernel" in entry:
+            self.set_estep_kernel(int(entry["estep_kernel"]))
+            if int(entry.get("rows_per_chunk", 0)):
+                self.set_slot_rows(int(entry["rows_per_chunk"]))
+            self.set_schedule(int(entry["waves_per_cell"]))
+            self.set_gather_lanes(int(entry.get("lanes_per_superpixel", 1)))
             self.init_seeds(lab)
+            self.tune_cached = True
             return self.get_schedule()
-        ms = np.zeros(3)
+        self.tune_cached = False
+        ms = np.zeros(_lib.TUNE_CANDIDATES)
         w = c_int32()
         check(lib().gmmsp_autotune(self.handle, self._lab(lab), int(passes),
                                    c_void_p(ms.ctypes.data), byref(w), c_void_p(self._stream())))
-        self.tune_ms = dict(zip((1, 2, 4), ms.tolist()))
+        # candidate 3 v + w: v = 0..2 slot-lane rows values (largest first), 3 pixel-lane
+        self.tune_ms = {f"v{v}w{(1, 2, 4)[i]}": float(ms[3 * v + i])
+                        for v in range(4) for i in range(3) if ms[3 * v + i] >= 0}
         gms = np.zeros(3)
         lanes = c_int32()
         check(lib().gmmsp_autotune_gather(self.handle, self._lab(lab), int(passes),
@@ -250,7 +284,9 @@ class GMMSP:
                                           c_void_p(self._stream())))
         self.tune_gather_ms = dict(zip((1, 4, 16), gms.tolist()))
         if path:
-            table[key] = {"waves_per_cell": w.value, "ms": self.tune_ms,
+            table[key] = {"estep_kernel": self.get_estep_kernel(),
+                          "rows_per_chunk": self.get_slot_rows(),
+                          "waves_per_cell": w.value, "ms": self.tune_ms,
                           "lanes_per_superpixel": lanes.value, "gather_ms": self.tune_gather_ms}
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:

@@ -1,6 +1,7 @@
-"""Schedules (waves per cell of the statistics pass, lanes per superpixel of
-the gather), the autotuners, graph replay and the 64-image uneven batch: every
-path against the oracle or bitwise against the eager single-image path."""
+"""Schedules (statistics-pass kind, rows per chunk and waves per cell, L fused
+into the statistics pass or not, lanes per superpixel of the gather), the
+autotuners, graph replay and the 64-image uneven batch: every path against the
+oracle or bitwise against the eager single-image path."""
 import os
 import sys
 
@@ -35,8 +36,15 @@ def cfg1():
     return im, g, ref
 
 
-def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None, lanes=1):
+def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None, lanes=1, kind=None, rows=None,
+        fused=None):
     m = GMMSP([(im.W, im.H)], K=K or im.K, device=dev)
+    if kind is not None:
+        m.set_estep_kernel(kind)
+    if rows is not None:
+        m.set_slot_rows(rows)
+    if fused is not None:
+        m.set_ll_fusion(fused)
     m.set_schedule(wpc)
     m.set_gather_lanes(lanes)
     m.set_graph_passes(graph)
@@ -59,6 +67,45 @@ def test_schedule_matches_oracle_and_repeats(dev, cfg1, wpc):
     assert np.abs(a["R"] - oracle_slots(g, ref["cand"], ref["R"])).max() <= 1e-4
 
 
+# every candidate the autotuner times on the 481x321 grid (v = 19: J = 3 columns
+# per lane, rows per chunk 3, 2, 1), L fused and not
+CANDIDATES = ([(1, r, w, f) for r in (3, 2, 1) for w in (1, 2, 4) for f in (1, 0)] +
+              [(0, None, w, None) for w in (1, 2, 4)])
+
+
+@pytest.mark.parametrize("kind,rows,wpc,fused", CANDIDATES)
+def test_every_tuned_candidate_matches_oracle(dev, cfg1, kind, rows, wpc, fused):
+    im, g, ref = cfg1
+    a = run(im, dev, 10, wpc, kind=kind, rows=rows, fused=fused)
+    assert_theta_close(a["theta"], O.theta_to_rows(ref["theta"]), 1e-3,
+                       what=f"kind {kind} rows {rows} wpc {wpc} fused {fused}")
+    np.testing.assert_allclose(a["hist"], ref["ll_hist"], rtol=1e-6)
+    assert np.abs(a["R"] - oracle_slots(g, ref["cand"], ref["R"])).max() <= 1e-4
+    if kind == 1:
+        # one wave per cell: every rows value gives the same pass bit for bit;
+        # the fused and separate L reductions differ in their grouping only
+        base = run(im, dev, 10, wpc, kind=1, rows=3 if wpc == 1 else rows, fused=1)
+        assert np.array_equal(a["theta"], base["theta"])
+        np.testing.assert_allclose(a["hist"], base["hist"], rtol=1e-13)
+        if fused:
+            assert np.array_equal(a["hist"], base["hist"])
+
+
+def test_slot_rows_restrictions(dev):
+    im = synth.config1_image()                 # v = 19: J = 3
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    assert m.get_estep_kernel() == 1 and m.get_slot_rows() == 3 and m.get_ll_fusion() == 1
+    for bad in (0, 4, 8, -1):
+        with pytest.raises(Exception):
+            m.set_slot_rows(bad)
+    m.set_estep_kernel(0)
+    assert m.get_ll_fusion() == 0              # the pixel-lane pass reduces L separately
+    big = GMMSP([(640, 480)], v=60, device=dev)  # cells wider than 56 pixels
+    assert big.get_estep_kernel() == 0 and big.get_slot_rows() == 0
+    with pytest.raises(Exception):
+        big.set_slot_rows(1)
+
+
 @pytest.mark.parametrize("wpc,graph,tol", [(1, 4, 0.0), (2, 3, 0.0), (1, 5, 1e-4), (4, 2, 1e-4)])
 def test_graph_replay_is_bitwise_eager(dev, wpc, graph, tol):
     im = synth.voronoi_lab(320, 240, 19, 3.0, 77, 200)
@@ -75,6 +122,27 @@ def test_graph_replay_is_bitwise_eager(dev, wpc, graph, tol):
         assert np.array_equal(m.get_params(), eager["theta"]), rep
         assert np.array_equal(m.ll_history(0), eager["hist"]), rep
         assert np.array_equal(it, eager["iters"]), rep
+
+
+def test_graph_replay_follows_schedule_changes(dev):
+    """A captured graph holds the kernels of its schedule: after the rows per
+    chunk, the L fusion or the gather lanes change, replay re-captures and
+    matches an eager run of the new schedule bit for bit."""
+    im = synth.voronoi_lab(320, 240, 19, 3.0, 77, 200)
+    lab = im.lab.reshape(-1).to(dev)
+    m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
+    m.set_schedule(2)
+    m.set_graph_passes(4)
+    for rows, fused, lanes in [(3, 1, 1), (1, 1, 1), (1, 0, 4), (2, 1, 16)]:
+        m.set_slot_rows(rows)
+        m.set_ll_fusion(fused)
+        m.set_gather_lanes(lanes)
+        m.init_seeds(lab)
+        it = m.em_iterate(lab, 30, 1e-4)
+        eager = run(im, dev, 30, 2, 0, 1e-4, rows=rows, fused=fused, lanes=lanes)
+        assert np.array_equal(m.get_params(), eager["theta"]), (rows, fused, lanes)
+        assert np.array_equal(m.ll_history(0), eager["hist"]), (rows, fused, lanes)
+        assert np.array_equal(it, eager["iters"]), (rows, fused, lanes)
 
 
 @pytest.mark.parametrize("wpc,lanes", [(1, 16), (4, 16), (1, 4), (2, 4)])
@@ -119,7 +187,11 @@ def test_autotune_picks_a_schedule(dev, tmp_path):
     cache = str(tmp_path / "schedules.json")
     w = m.autotune(lab, passes=2, cache=cache)
     assert w in (1, 2, 4) and m.get_schedule() == w
-    assert os.path.exists(cache) and set(m.tune_ms) == {1, 2, 4}
+    vmax = max(g.vx for g in m.grids)
+    J = -(-vmax // 7)
+    n_rows = {1: 3, 2: 3, 3: 3, 4: 2, 5: 2 if vmax <= 32 else 1}.get(J, 1)
+    assert os.path.exists(cache) and len(m.tune_ms) == 3 * (n_rows + 1)
+    assert all(v > 0 for v in m.tune_ms.values())
     assert set(m.tune_gather_ms) == {1, 4, 16} and m.get_gather_lanes() in (1, 4, 16)
     assert all(v > 0 for v in m.tune_gather_ms.values())
     say("autotune ms", m.tune_ms, "picked", w, "gather ms", m.tune_gather_ms,
@@ -129,7 +201,7 @@ def test_autotune_picks_a_schedule(dev, tmp_path):
     assert list(it) == [3] * 6
     m2 = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
     assert m2.autotune(lab, passes=2, cache=cache) == w          # from the cache
-    assert m2.get_gather_lanes() == m.get_gather_lanes()
+    assert m2.tune_cached and m2.schedule() == m.schedule()
     m2.em_iterate(lab, 3)
     assert np.array_equal(m.get_params(), m2.get_params())
 
