@@ -151,6 +151,9 @@ int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream);
  * stops at the first pass t >= 1 with |L_t - L_(t-1)| <= rel_tol |L_(t-1)| and
  * keeps theta^t; with rel_tol <= 0 every image runs exactly max_iters passes
  * (the paper's fixed T).  Images that have stopped are skipped by every kernel.
+ * A pass is three launches (statistics, L with the stop rule, gather), or two
+ * with rel_tol <= 0, where nothing in the pass waits for L and the gather's
+ * launch also forms it (the same fixed-order sum either way).
  * Calls accumulate: a second call continues from the current theta.
  * iters_host (nullable, n_images int32): M-steps applied per image since the
  * last initialisation.  Synchronises `stream`. */
@@ -213,17 +216,8 @@ int gmmsp_get_estep_kernel(const gmmsp_handle* h, int32_t* kind);
 int gmmsp_set_slot_rows(gmmsp_handle* h, int32_t rows);
 int gmmsp_get_slot_rows(const gmmsp_handle* h, int32_t* rows);
 
-/* Log-likelihood fusion (Algorithm 1's stop rule): with on = 1 (default) the
- * slot-lane pass also forms L(theta^t) per image -- the image's last cell wave
- * to finish adds the per-wave terms in a fixed order -- and applies the stop
- * rule, so an em pass is two launches (statistics, gather); with 0, or with
- * the pixel-lane pass, a separate reduction kernel does it (its sums are
- * grouped differently).  get reports whether fusion is in effect. */
-int gmmsp_set_ll_fusion(gmmsp_handle* h, int32_t on);
-int gmmsp_get_ll_fusion(const gmmsp_handle* h, int32_t* on);
-
-/* Autotuner of the statistics pass: for each candidate schedule, `passes`
- * statistics passes with L(theta^t) (after three untimed) from the grid
+/* Autotuner of the statistics pass: for each candidate schedule, `passes` em
+ * passes (statistics, L, gather; after three untimed) from the grid
  * initialisation, timed with HIP events on `stream`.  Candidates, in order of
  * preference: the slot-lane pass (kind 1) with each built rows-per-chunk value,
  * largest first, then the pixel-lane pass (kind 0); 1, 2 and 4 waves per cell

@@ -67,8 +67,6 @@ _SIGS = {
     "gmmsp_get_estep_kernel": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_set_slot_rows": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_slot_rows": (c_int, [c_void_p, POINTER(c_int32)]),
-    "gmmsp_set_ll_fusion": (c_int, [c_void_p, c_int32]),
-    "gmmsp_get_ll_fusion": (c_int, [c_void_p, POINTER(c_int32)]),
     "gmmsp_autotune": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32), c_void_p]),
     "gmmsp_set_gather_lanes": (c_int, [c_void_p, c_int32]),
     "gmmsp_get_gather_lanes": (c_int, [c_void_p, POINTER(c_int32)]),

@@ -1,9 +1,9 @@
 """Per-iteration rates of the EM on the benchmark workloads, paper T mode (a
 fixed number of iterations, Algorithm 1): 481x321 (K 400, T = 10), 1920x1080
 (K 2000, T = 20), the uneven batch of 64 images (T = 15) and the 4K batch
-(32 x 3840x2160, K 10000, T = 10).  Each workload is autotuned (waves per
-cell of the statistics pass, lanes per superpixel of the gather), then timed
-with graph replay:
+(32 x 3840x2160, K 10000, T = 10).  Each workload is autotuned (kind, rows per
+chunk and waves per cell of the statistics pass, lanes per superpixel of the
+gather), then timed eagerly and with graph replay (the faster counts):
 
   * Mpix/s per iteration = total pixels x iterations / wall time of the
     iterations (E-step, statistics, gather, LL and stop rule; inputs resident);
@@ -77,6 +77,61 @@ def end_to_end(dev, repeats: int):
         m.close()
 
 
+def measure(c: int, dev, repeats: int = 5) -> dict:
+    """Per-iteration rates of workload c: autotuned schedule, wall time of T
+    iterations eager and with graph replay (median of `repeats`), and the
+    E-step alone from HIP events in one more eager run."""
+    name, ims, T = workload(c, dev)
+    lab = synth.pack_batch(ims).contiguous()
+    m = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
+    m.autotune(lab, passes=3, cache=None)
+    sched = m.schedule()
+
+    def wall(graph: int) -> float:
+        m.set_graph_passes(graph)
+        m.init_seeds(lab)
+        m.em_iterate(lab, T)                        # warm-up (graph capture)
+        walls = []
+        for _ in range(repeats):
+            m.init_seeds(lab)
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            m.em_iterate(lab, T)
+            torch.cuda.synchronize(dev)
+            walls.append(time.perf_counter() - t0)
+        return float(np.median(walls))
+
+    t_eager, t_graph = wall(0), wall(T)
+    t = min(t_eager, t_graph)
+    # the E-step alone: an eager run with events around each launch (the
+    # library replays no graph while it profiles)
+    m.set_graph_passes(0)
+    m.profile(True)
+    m.profile_read(True)
+    m.init_seeds(lab)
+    m.em_iterate(lab, T)
+    p = m.profile_read(True)
+    m.profile(False)
+    est = p["estep_ms"] / p["launches"]
+    tflops = p["pair_evals"] * FLOPS_PER_PAIR / (p["estep_ms"] / 1e3) / 1e12
+    r = dict(config=c, workload=name, images=len(ims), pixels=m.n_pixels, T=T,
+             schedule=sched, statistics_pass_ms=m.tune_ms,
+             gather_ms={k: round(v, 4) for k, v in m.tune_gather_ms.items()},
+             mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
+             ms_per_iteration=round(1e3 * t / T, 4),
+             ms_per_iteration_eager=round(1e3 * t_eager / T, 4),
+             ms_per_iteration_graph=round(1e3 * t_graph / T, 4),
+             estep_ms_per_launch=round(est, 4),
+             estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
+             pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),
+             estep_tflops=round(tflops, 2), frac_of_157_3=round(tflops / PEAK_FP32, 3),
+             frac_of_78_6=round(tflops / PEAK_SINGLE, 3))
+    m.close()
+    del m, lab, ims
+    torch.cuda.empty_cache()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--configs", type=str, default="1,2,3,5")
@@ -85,57 +140,23 @@ def main():
     dev = torch.device("cuda:0")
     rows = []
     for c in (int(x) for x in args.configs.split(",")):
-        name, ims, T = workload(c, dev)
-        lab = synth.pack_batch(ims).contiguous()
-        m = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
-        wpc = m.autotune(lab, passes=3, cache=None)
-        m.set_graph_passes(T)
-        m.init_seeds(lab)
-        m.em_iterate(lab, T)                        # warm-up (graph capture)
-        walls = []
-        for _ in range(args.repeats):
-            m.init_seeds(lab)
-            torch.cuda.synchronize(dev)
-            t0 = time.perf_counter()
-            m.em_iterate(lab, T)
-            torch.cuda.synchronize(dev)
-            walls.append(time.perf_counter() - t0)
-        # the E-step alone: an eager run with events around each launch (the
-        # library replays no graph while it profiles)
-        m.profile(True)
-        m.profile_read(True)
-        m.init_seeds(lab)
-        m.em_iterate(lab, T)
-        p = m.profile_read(True)
-        m.profile(False)
-        t = float(np.median(walls))
-        est = p["estep_ms"] / p["launches"]
-        tflops = p["pair_evals"] * FLOPS_PER_PAIR / (p["estep_ms"] / 1e3) / 1e12
-        r = dict(config=c, workload=name, images=len(ims), pixels=m.n_pixels, T=T,
-                 waves_per_cell=wpc, gather_lanes=m.get_gather_lanes(),
-                 gather_ms={k: round(v, 4) for k, v in m.tune_gather_ms.items()},
-                 mpix_per_s_per_iteration=round(m.n_pixels * T / t / 1e6, 1),
-                 ms_per_iteration=round(1e3 * t / T, 4), estep_ms_per_launch=round(est, 4),
-                 estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
-                 pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),
-                 estep_tflops=round(tflops, 2), frac_of_157_3=round(tflops / PEAK_FP32, 3),
-                 frac_of_78_6=round(tflops / PEAK_SINGLE, 3))
+        r = measure(c, dev, args.repeats)
         print(json.dumps(r), flush=True)
         rows.append(r)
-        m.close()
-        del m, lab, ims
-        torch.cuda.empty_cache()
     if 1 in [int(x) for x in args.configs.split(",")]:
         end_to_end(dev, args.repeats)
-    print("| workload | Mpix/s per iteration | ms per iteration | E-step us | E-step Gpx/s | "
-          "TFLOP/s | of 157.3 | of 78.6 | waves per cell | gather lanes |")
-    print("|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+    print("| workload | Mpix/s per iteration | ms per iteration (eager / graph) | E-step us | "
+          "E-step Gpx/s | TFLOP/s | of 157.3 | schedule (kind, rows, waves per cell, "
+          "gather lanes) |")
+    print("|---|---:|---|---:|---:|---:|---:|---|")
     for r in rows:
-        print(f"| {r['workload']} | {r['mpix_per_s_per_iteration']:.0f} | {r['ms_per_iteration']:.3f} | "
+        sc = r["schedule"]
+        print(f"| {r['workload']} | {r['mpix_per_s_per_iteration']:.0f} | "
+              f"{r['ms_per_iteration_eager']:.4f} / {r['ms_per_iteration_graph']:.4f} | "
               f"{1e3 * r['estep_ms_per_launch']:.0f} | {r['estep_gpx_per_s']:.1f} | "
-              f"{r['estep_tflops']:.1f} | {r['frac_of_157_3']:.2f} | {r['frac_of_78_6']:.2f} | "
-              f"{r['waves_per_cell']} | "
-              f"{r['gather_lanes']} |")
+              f"{r['estep_tflops']:.1f} | {r['frac_of_157_3']:.2f} | "
+              f"{sc['estep_kernel']}, {sc['rows_per_chunk']}, {sc['waves_per_cell']}, "
+              f"{sc['gather_lanes']} |")
 
 
 if __name__ == "__main__":

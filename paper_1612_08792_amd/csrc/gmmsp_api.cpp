@@ -204,7 +204,7 @@ struct gmmsp_handle {
   hipGraphExec_t gexec = nullptr;
   const float* g_lab = nullptr;
   double g_tol = 0.0;
-  int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1, g_rc = 0, g_fuse = -1;
+  int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1, g_rc = 0;
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -308,7 +308,6 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   for (const ImgDesc& d : descs) max_vx = std::max(max_vx, d.vx);
   P.estep = 0;
   if (P.cov_mode == 0 && slots_shape(max_vx, &P.slot_j, &P.slot_rc)) P.estep = 1;
-  P.fuse_ll = 1;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -404,19 +403,22 @@ int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream) {
 
 namespace {
 
-// One em pass (Algorithm 1): the statistics pass with L(theta^t) and the stop
-// rule, then the M-step gather.  a and b (nullable) bracket the statistics
-// pass with events.
+// One em pass (Algorithm 1): the statistics pass, L(theta^t) and the stop
+// rule, then the M-step gather.  Without the stop rule (rel_tol 0) no step of
+// the pass waits for L, and the gather's launch forms it too: two launches.
+// a and b (nullable) bracket the statistics pass with events.
 hipError_t em_pass(const DevPtrs& P, const float* lab, double rel_tol, hipStream_t s, hipEvent_t a,
                    hipEvent_t b) {
-  const bool fused = ll_fused(P);
   hipError_t e = hipSuccess;
   if (a) e = hipEventRecord(a, s);
-  if (e == hipSuccess)
-    e = fused ? launch_estep_ll(P, lab, LL_EM, rel_tol, s) : launch_estep_stats(P, lab, s);
+  if (e == hipSuccess) e = launch_estep_stats(P, lab, s);
   if (e == hipSuccess && b) e = hipEventRecord(b, s);
-  if (e == hipSuccess && !fused) e = launch_ll_update(P, rel_tol, s);
-  if (e == hipSuccess) e = launch_finalize(P, s);
+  if (rel_tol > 0.0) {
+    if (e == hipSuccess) e = launch_ll_update(P, rel_tol, s);
+    if (e == hipSuccess) e = launch_finalize(P, s);
+  } else if (e == hipSuccess) {
+    e = launch_finalize(P, s, true);
+  }
   return e;
 }
 
@@ -445,7 +447,6 @@ int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t le
   h->g_glanes = h->P.glanes;
   h->g_estep = h->P.estep;
   h->g_rc = h->P.slot_rc;
-  h->g_fuse = h->P.fuse_ll;
   return GMMSP_OK;
 }
 
@@ -461,8 +462,7 @@ int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, doubl
   const int32_t G = h->graph_passes;
   // the graph holds the kernels and arguments of the schedule it was captured with
   if (!h->gexec || h->g_lab != lab || h->g_tol != rel_tol || h->g_len != G || h->g_wpc != h->P.wpc ||
-      h->g_glanes != h->P.glanes || h->g_estep != h->P.estep || h->g_rc != h->P.slot_rc ||
-      h->g_fuse != h->P.fuse_ll) {
+      h->g_glanes != h->P.glanes || h->g_estep != h->P.estep || h->g_rc != h->P.slot_rc) {
     int rc = capture_passes(h, lab, rel_tol, G);
     if (rc) return rc;
   }
@@ -681,19 +681,6 @@ int gmmsp_get_slot_rows(const gmmsp_handle* h, int32_t* rows) {
   return GMMSP_OK;
 }
 
-int gmmsp_set_ll_fusion(gmmsp_handle* h, int32_t on) {
-  if (!h) return fail(GMMSP_E_INVAL, "null handle");
-  if (on != 0 && on != 1) return fail(GMMSP_E_INVAL, "fusion flag must be 0 or 1");
-  h->P.fuse_ll = on;
-  return GMMSP_OK;
-}
-
-int gmmsp_get_ll_fusion(const gmmsp_handle* h, int32_t* on) {
-  if (!h || !on) return fail(GMMSP_E_INVAL, "null pointer");
-  *on = ll_fused(h->P) ? 1 : 0;
-  return GMMSP_OK;
-}
-
 int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (lanes_per_superpixel != 1 && lanes_per_superpixel != 4 && lanes_per_superpixel != 16)
@@ -763,13 +750,12 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
     if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
     double tot = 0.0;
     // kTuneWarm untimed passes (the first passes from the grid seeds run
-    // slower than later ones), then `passes` timed ones: the statistics pass
-    // with L(theta^t) and the stop rule (one launch where they are fused)
+    // slower than later ones), then `passes` timed ones: whole em passes, as
+    // the waves per cell also set the work of the gather
     for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
       e = hipEventRecord(a, s);
-      if (e == hipSuccess) e = launch_estep_ll(h->P, lab_dev, LL_EM, 0.0, s);
+      if (e == hipSuccess) e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
       if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = launch_finalize(h->P, s);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);

@@ -86,9 +86,7 @@ struct ImgState {           // 40 bytes
   int32_t fallback;         // 1: the guarded warm start kept the grid seeds
   double ll_final;          // L(theta) of the last labelling (or evaluation) pass
   double ll_seed;           // L(theta^0) of the grid seeds (guarded warm start)
-  int32_t arrive;           // cell waves of the running statistics pass that have
-                            // finished (the pass with L fused in); 0 between passes
-  int32_t pad;
+  double pad;
 };
 
 struct CellDesc { int32_t img, cx, cy, pad; };
@@ -116,14 +114,12 @@ struct DevPtrs {
                             // lane (k_cells), 1 one candidate slot per lane (k_slots,
                             // gmmsp_slots.hip; its colour statistics are whitened)
   int32_t slot_j, slot_rc;  // k_slots shape: columns per lane, rows per chunk
-  int32_t fuse_ll;          // 1: k_slots also forms L(theta^t) and applies the stop rule
-                            // (its image's last cell wave), so an EM pass is two launches
 };
 
 // How a per-image log-likelihood L(theta^t) is committed: LL_EM appends it to
 // the image's history and applies the stop rule; LL_FINAL and LL_SEED store it
 // (ll_final, ll_seed) and change no EM state.
-enum LLMode { LL_NONE = -1, LL_EM = 0, LL_FINAL = 1, LL_SEED = 2 };
+enum LLMode { LL_EM = 0, LL_FINAL = 1, LL_SEED = 2 };
 
 // The stop rule of Algorithm 1 on image b's L = L(theta^t): the run stops when
 // |L - L(theta^(t-1))| <= rel_tol |L(theta^(t-1))| (rel_tol > 0); otherwise
@@ -168,13 +164,12 @@ hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s
 hipError_t launch_reset_state(const DevPtrs& P, hipStream_t s);
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s);
 hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s);
-// true when the statistics pass commits L itself (launch_estep_ll)
-inline bool ll_fused(const DevPtrs& P) { return P.cov_mode == 0 && P.estep == 1 && P.fuse_ll; }
-// the statistics pass and L(theta^t) committed in `mode`: one launch when
-// ll_fused(P), else the statistics pass and k_ll_reduce
+// the statistics pass, then L(theta^t) per image (k_ll_reduce) committed in `mode`
 hipError_t launch_estep_ll(const DevPtrs& P, const float* lab, int mode, double rel_tol,
                            hipStream_t s);
-hipError_t launch_finalize(const DevPtrs& P, hipStream_t s);
+// the M-step gather; with_ll: also L(theta^t) of every image in the EM pass
+// without the stop rule (rel_tol 0), as extra blocks of the same launch
+hipError_t launch_finalize(const DevPtrs& P, hipStream_t s, bool with_ll = false);
 hipError_t launch_label(const DevPtrs& P, const float* lab, int32_t* labels, hipStream_t s);
 hipError_t launch_export_R(const DevPtrs& P, const float* lab, float* R, hipStream_t s);
 hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t s);
@@ -183,11 +178,10 @@ hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t
 // columns per lane and the largest rows per chunk for cells up to max_w pixels
 // wide (0 when the kernel does not cover that width); slots_rows lists the
 // rows-per-chunk values built for J columns per lane (largest first) and
-// returns their count.  ll_mode LL_NONE leaves L to k_ll_reduce.
+// returns their count.
 int slots_shape(int max_w, int* J, int* RC);
 int slots_rows(int J, int max_rc, int* rows, int cap);
-hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, int ll_mode, double rel_tol,
-                              hipStream_t s);
+hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s);
 
 // The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
 // 2 responsibilities, 3 candidates.

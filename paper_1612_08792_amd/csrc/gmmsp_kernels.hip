@@ -159,7 +159,6 @@ __global__ __launch_bounds__(256) void k_reset_state(DevPtrs P) {
   st->done = 0;
   st->iters = 0;
   st->ll_final = 0.0;
-  st->arrive = 0;
 }
 
 // Sec. III-C: mu_k = z_j at the seed pixel, Sigma_s = diag(v_x^2, v_y^2),
@@ -566,21 +565,18 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
 // ---------------------------------------------------------------------------
 // L(theta^t) per image and the stop rule; one block per image
 // ---------------------------------------------------------------------------
-constexpr int kLLThreads = 1024;
+constexpr int kLLThreads = 256;
 
-// final_pass: LL_EM the EM pass (history, stop rule), LL_FINAL L into
-// ll_final, LL_SEED L into ll_seed (the last two change no EM state)
-__global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_tol, int final_pass,
-                                                          int nsub) {
+// L(theta^t) of image b from its cell waves' terms, committed in `mode` (see
+// ll_commit); one block of kLLThreads threads.  Fixed order: thread i adds
+// cells i, i + kLLThreads, ... of each wave set in turn, then a fixed tree.
+// With LL_EM an image that has stopped is skipped.
+__device__ inline void ll_reduce_block(const DevPtrs& P, int b, double rel_tol, int mode,
+                                       int nsub) {
   __shared__ double red[kLLThreads];
-  const int b = blockIdx.x;
   const ImgDesc* I = P.img + b;
-  ImgState* st = P.state + b;
-  const int done = st->done;
-  if (!final_pass && done) return;
+  if (mode == LL_EM && P.state[b].done) return;
   const int ncells = I->ncells;
-  // fixed order: thread i sums cells i, i + 1024, ... of every cell wave, then
-  // a fixed tree; consecutive threads read consecutive cells
   double s = 0.0;
   for (int u = 0; u < nsub; ++u) {
     const double* llp = P.llp + (size_t)u * P.n_cell + I->cell_off;
@@ -593,7 +589,14 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) ll_commit(P, b, red[0], final_pass, rel_tol);
+  if (threadIdx.x == 0) ll_commit(P, b, red[0], mode, rel_tol);
+}
+
+// mode: LL_EM the EM pass (history, stop rule), LL_FINAL L into ll_final,
+// LL_SEED L into ll_seed (the last two change no EM state)
+__global__ __launch_bounds__(kLLThreads) void k_ll_reduce(DevPtrs P, double rel_tol, int mode,
+                                                          int nsub) {
+  ll_reduce_block(P, blockIdx.x, rel_tol, mode, nsub);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,8 +696,14 @@ __device__ inline bool theta_from_stats(double (&acc)[kStats], const SpDesc& d,
   return true;
 }
 
-// One thread per superpixel: the window cells in fixed (dy, dx) order.
-__global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
+// One thread per superpixel: the window cells in fixed (dy, dx) order.  Blocks
+// from n_fin on take L(theta^t) of image blockIdx.x - n_fin in the EM pass
+// without the stop rule (nothing in this pass depends on it then).
+__global__ __launch_bounds__(256) void k_finalize(DevPtrs P, int n_fin) {
+  if ((int)blockIdx.x >= n_fin) {
+    ll_reduce_block(P, blockIdx.x - n_fin, 0.0, LL_EM, P.wpc);
+    return;
+  }
   const int sp = blockIdx.x * 256 + threadIdx.x;
   if (sp >= P.n_sp) return;
   const SpDesc d = P.sp[sp];
@@ -726,8 +735,12 @@ __global__ __launch_bounds__(256) void k_finalize(DevPtrs P) {
 // differently from k_finalize, so the schedules agree up to FP64 rounding;
 // each is bitwise repeatable.
 template <int G>
-__global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P) {
+__global__ __launch_bounds__(256) void k_finalize_lanes(DevPtrs P, int n_fin) {
   static_assert(G == 4 || G == 16, "4 or 16 lanes per superpixel");
+  if ((int)blockIdx.x >= n_fin) {
+    ll_reduce_block(P, blockIdx.x - n_fin, 0.0, LL_EM, P.wpc);
+    return;
+  }
   const int lane = threadIdx.x & (G - 1);
   const int sp = blockIdx.x * (256 / G) + threadIdx.x / G;
   if (sp >= P.n_sp) return;  // the whole group of G lanes
@@ -805,7 +818,7 @@ hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s
 
 hipError_t launch_estep_stats(const DevPtrs& P, const float* lab, hipStream_t s) {
   if (P.cov_mode) return launch_alt_cells(P, 0, lab, nullptr, nullptr, s);
-  if (P.estep == 1) return launch_estep_slots(P, lab, LL_NONE, 0.0, s);
+  if (P.estep == 1) return launch_estep_slots(P, lab, s);
   const dim3 grid(blocks_for((size_t)P.n_cell * P.wpc, kWavesPerBlock));
   if (P.wpc == 4)
     hipLaunchKernelGGL((k_cells<M_STATS, 4>), grid, dim3(256), 0, s, P, lab, (int32_t*)nullptr,
@@ -827,21 +840,27 @@ hipError_t launch_ll_update(const DevPtrs& P, double rel_tol, hipStream_t s) {
 
 hipError_t launch_estep_ll(const DevPtrs& P, const float* lab, int mode, double rel_tol,
                            hipStream_t s) {
-  if (ll_fused(P)) return launch_estep_slots(P, lab, mode, rel_tol, s);
   hipError_t e = launch_estep_stats(P, lab, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, rel_tol, mode, P.wpc);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DevPtrs& P, hipStream_t s) {
-  if (P.cov_mode) return launch_alt_finalize(P, s);
+hipError_t launch_finalize(const DevPtrs& P, hipStream_t s, bool with_ll) {
+  if (P.cov_mode) {
+    hipError_t e = hipSuccess;
+    if (with_ll) e = launch_ll_update(P, 0.0, s);
+    return e == hipSuccess ? launch_alt_finalize(P, s) : e;
+  }
+  const int per = 256 / P.glanes;  // superpixels per block
+  const int n_fin = (int)blocks_for(P.n_sp, per);
+  const dim3 grid(n_fin + (with_ll ? P.n_img : 0));
   if (P.glanes == 16)
-    hipLaunchKernelGGL(k_finalize_lanes<16>, dim3(blocks_for(P.n_sp, 256 / 16)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_finalize_lanes<16>, grid, dim3(256), 0, s, P, n_fin);
   else if (P.glanes == 4)
-    hipLaunchKernelGGL(k_finalize_lanes<4>, dim3(blocks_for(P.n_sp, 256 / 4)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_finalize_lanes<4>, grid, dim3(256), 0, s, P, n_fin);
   else
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(P.n_sp, 256)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, s, P, n_fin);
   return hipGetLastError();
 }
 

@@ -17,10 +17,6 @@
 //            denominator), takes the reciprocal and the log-likelihood term;
 //   phase 3  every (slot, phase) lane forms R = e / sum for its pixels and
 //            adds them to its slot's statistics.
-// With L fused in, the image's last cell wave to finish (an arrival count per
-// image) adds the image's per-wave log-likelihood terms in a fixed order and
-// commits L(theta^t): the stop rule of Algorithm 1 then needs no launch of
-// its own.
 // Spatial statistics use per-column accumulators (a lane's columns are fixed,
 // its row is wave-uniform); colour statistics are taken in the record's
 // whitened colour coordinates (w, u1, u2), which the density computes anyway,
@@ -68,7 +64,7 @@ __device__ __forceinline__ float vreg(float x) {
 
 template <int J, int RC, int WPC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
-    DevPtrs P, const float* __restrict__ lab, int ll_mode, double rel_tol) {
+    DevPtrs P, const float* __restrict__ lab) {
   // products are rounded where written: every shape of the kernel rounds alike
 #pragma clang fp contract(off)
   using LL = SlotLds<J, RC>;
@@ -333,27 +329,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   for (int m = 32; m >= 1; m >>= 1) ll += __shfl_xor(ll, m, 64);
   const double cst = sub == 0 ? (double)(w * h) * Ip->lncmax : 0.0;
   if (lane == 0) P.llp[(size_t)sub * P.n_cell + cell] = kLn2 * (ll * 0x1p-22) + cst;
-  if (ll_mode == LL_NONE) return;
-  // this wave's term is visible device-wide before its arrival counts
-  __threadfence();
-  int before = 0;
-  if (lane == 0) before = atomicAdd(&P.state[b].arrive, 1);
-  before = __shfl(before, 0, 64);
-  const int ncells = Ip->ncells;
-  if (before != ncells * WPC - 1) return;
-  __threadfence();  // every other wave's term of the image is visible to this one
-  // lane i adds the terms of cells i, i + 64, ... of each wave set in turn, then
-  // a butterfly: the order does not depend on which wave finished last
-  const double* lp = P.llp + Ip->cell_off;
-  double acc = 0.0;
-  for (int u = 0; u < WPC; ++u)
-    for (int c = lane; c < ncells; c += 64) acc += lp[(size_t)u * P.n_cell + c];
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-  if (lane == 0) {
-    P.state[b].arrive = 0;
-    ll_commit(P, b, acc, ll_mode, rel_tol);
-  }
 }
 
 // Columns per lane and rows per chunk for cells up to max_w wide: J = ceil(max_w / 7),
@@ -378,15 +353,14 @@ int slots_shape(int max_w, int* J, int* RC) {
 
 namespace {
 template <int J, int RC>
-hipError_t launch_jrc(const DevPtrs& P, const float* lab, int ll_mode, double rel_tol,
-                      hipStream_t s) {
+hipError_t launch_jrc(const DevPtrs& P, const float* lab, hipStream_t s) {
   const dim3 grid((unsigned)(((size_t)P.n_cell * P.wpc + kWavesPerBlock - 1) / kWavesPerBlock));
   if (P.wpc == 4)
-    hipLaunchKernelGGL((k_slots<J, RC, 4>), grid, dim3(256), 0, s, P, lab, ll_mode, rel_tol);
+    hipLaunchKernelGGL((k_slots<J, RC, 4>), grid, dim3(256), 0, s, P, lab);
   else if (P.wpc == 2)
-    hipLaunchKernelGGL((k_slots<J, RC, 2>), grid, dim3(256), 0, s, P, lab, ll_mode, rel_tol);
+    hipLaunchKernelGGL((k_slots<J, RC, 2>), grid, dim3(256), 0, s, P, lab);
   else
-    hipLaunchKernelGGL((k_slots<J, RC, 1>), grid, dim3(256), 0, s, P, lab, ll_mode, rel_tol);
+    hipLaunchKernelGGL((k_slots<J, RC, 1>), grid, dim3(256), 0, s, P, lab);
   return hipGetLastError();
 }
 }  // namespace
@@ -403,11 +377,10 @@ int slots_rows(int J, int max_rc, int* rows, int cap) {
   return n;
 }
 
-hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, int ll_mode, double rel_tol,
-                              hipStream_t s) {
+hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s) {
   const int J = P.slot_j, RC = P.slot_rc;
 #define GMMSP_JRC(j, rc) \
-  if (J == j && RC == rc) return launch_jrc<j, rc>(P, lab, ll_mode, rel_tol, s);
+  if (J == j && RC == rc) return launch_jrc<j, rc>(P, lab, s);
   GMMSP_JRC(1, 8) GMMSP_JRC(1, 4) GMMSP_JRC(1, 2)
   GMMSP_JRC(2, 4) GMMSP_JRC(2, 2) GMMSP_JRC(2, 1)
   GMMSP_JRC(3, 3) GMMSP_JRC(3, 2) GMMSP_JRC(3, 1)

@@ -202,22 +202,11 @@ class GMMSP:
         check(lib().gmmsp_get_slot_rows(self.handle, byref(r)))
         return r.value
 
-    def set_ll_fusion(self, on: bool):
-        """L(theta^t) and the stop rule inside the slot-lane pass (1) or in a
-        reduction kernel of their own (0)."""
-        check(lib().gmmsp_set_ll_fusion(self.handle, int(bool(on))))
-
-    def get_ll_fusion(self) -> int:
-        r = c_int32()
-        check(lib().gmmsp_get_ll_fusion(self.handle, byref(r)))
-        return r.value
-
     def schedule(self) -> dict:
         """The schedule in effect: statistics-pass kind, rows per chunk, waves
-        per cell, gather lanes, L fusion."""
+        per cell, gather lanes."""
         return {"estep_kernel": self.get_estep_kernel(), "rows_per_chunk": self.get_slot_rows(),
-                "waves_per_cell": self.get_schedule(), "gather_lanes": self.get_gather_lanes(),
-                "ll_fused": self.get_ll_fusion()}
+                "waves_per_cell": self.get_schedule(), "gather_lanes": self.get_gather_lanes()}
 
     def set_gather_lanes(self, lanes_per_superpixel: int):
         check(lib().gmmsp_set_gather_lanes(self.handle, int(lanes_per_superpixel)))

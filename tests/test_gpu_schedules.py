@@ -1,7 +1,7 @@
-"""Schedules (statistics-pass kind, rows per chunk and waves per cell, L fused
-into the statistics pass or not, lanes per superpixel of the gather), the
-autotuners, graph replay and the 64-image uneven batch: every path against the
-oracle or bitwise against the eager single-image path."""
+"""Schedules (statistics-pass kind, rows per chunk and waves per cell, lanes
+per superpixel of the gather), the autotuners, graph replay and the 64-image
+uneven batch: every path against the oracle or bitwise against the eager
+single-image path."""
 import os
 import sys
 
@@ -36,15 +36,12 @@ def cfg1():
     return im, g, ref
 
 
-def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None, lanes=1, kind=None, rows=None,
-        fused=None):
+def run(im, dev, T, wpc=1, graph=0, rel_tol=0.0, K=None, lanes=1, kind=None, rows=None):
     m = GMMSP([(im.W, im.H)], K=K or im.K, device=dev)
     if kind is not None:
         m.set_estep_kernel(kind)
     if rows is not None:
         m.set_slot_rows(rows)
-    if fused is not None:
-        m.set_ll_fusion(fused)
     m.set_schedule(wpc)
     m.set_gather_lanes(lanes)
     m.set_graph_passes(graph)
@@ -68,38 +65,34 @@ def test_schedule_matches_oracle_and_repeats(dev, cfg1, wpc):
 
 
 # every candidate the autotuner times on the 481x321 grid (v = 19: J = 3 columns
-# per lane, rows per chunk 3, 2, 1), L fused and not
-CANDIDATES = ([(1, r, w, f) for r in (3, 2, 1) for w in (1, 2, 4) for f in (1, 0)] +
-              [(0, None, w, None) for w in (1, 2, 4)])
+# per lane, rows per chunk 3, 2, 1)
+CANDIDATES = [(1, r, w) for r in (3, 2, 1) for w in (1, 2, 4)] + [(0, None, w) for w in (1, 2, 4)]
 
 
-@pytest.mark.parametrize("kind,rows,wpc,fused", CANDIDATES)
-def test_every_tuned_candidate_matches_oracle(dev, cfg1, kind, rows, wpc, fused):
+@pytest.mark.parametrize("kind,rows,wpc", CANDIDATES)
+def test_every_tuned_candidate_matches_oracle(dev, cfg1, kind, rows, wpc):
     im, g, ref = cfg1
-    a = run(im, dev, 10, wpc, kind=kind, rows=rows, fused=fused)
+    a = run(im, dev, 10, wpc, kind=kind, rows=rows)
     assert_theta_close(a["theta"], O.theta_to_rows(ref["theta"]), 1e-3,
-                       what=f"kind {kind} rows {rows} wpc {wpc} fused {fused}")
+                       what=f"kind {kind} rows {rows} wpc {wpc}")
     np.testing.assert_allclose(a["hist"], ref["ll_hist"], rtol=1e-6)
     assert np.abs(a["R"] - oracle_slots(g, ref["cand"], ref["R"])).max() <= 1e-4
-    if kind == 1:
-        # one wave per cell: every rows value gives the same pass bit for bit;
-        # the fused and separate L reductions differ in their grouping only
-        base = run(im, dev, 10, wpc, kind=1, rows=3 if wpc == 1 else rows, fused=1)
+    b = run(im, dev, 10, wpc, kind=kind, rows=rows)
+    assert np.array_equal(a["theta"], b["theta"]) and np.array_equal(a["hist"], b["hist"])
+    if kind == 1 and wpc == 1 and rows != 3:
+        # one wave per cell: every rows value gives the same passes bit for bit
+        base = run(im, dev, 10, 1, kind=1, rows=3)
         assert np.array_equal(a["theta"], base["theta"])
-        np.testing.assert_allclose(a["hist"], base["hist"], rtol=1e-13)
-        if fused:
-            assert np.array_equal(a["hist"], base["hist"])
+        assert np.array_equal(a["hist"], base["hist"])
 
 
 def test_slot_rows_restrictions(dev):
     im = synth.config1_image()                 # v = 19: J = 3
     m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
-    assert m.get_estep_kernel() == 1 and m.get_slot_rows() == 3 and m.get_ll_fusion() == 1
+    assert m.get_estep_kernel() == 1 and m.get_slot_rows() == 3
     for bad in (0, 4, 8, -1):
         with pytest.raises(Exception):
             m.set_slot_rows(bad)
-    m.set_estep_kernel(0)
-    assert m.get_ll_fusion() == 0              # the pixel-lane pass reduces L separately
     big = GMMSP([(640, 480)], v=60, device=dev)  # cells wider than 56 pixels
     assert big.get_estep_kernel() == 0 and big.get_slot_rows() == 0
     with pytest.raises(Exception):
@@ -126,23 +119,23 @@ def test_graph_replay_is_bitwise_eager(dev, wpc, graph, tol):
 
 def test_graph_replay_follows_schedule_changes(dev):
     """A captured graph holds the kernels of its schedule: after the rows per
-    chunk, the L fusion or the gather lanes change, replay re-captures and
+    chunk, the pass kind or the gather lanes change, replay re-captures and
     matches an eager run of the new schedule bit for bit."""
     im = synth.voronoi_lab(320, 240, 19, 3.0, 77, 200)
     lab = im.lab.reshape(-1).to(dev)
     m = GMMSP([(im.W, im.H)], K=im.K, device=dev)
     m.set_schedule(2)
     m.set_graph_passes(4)
-    for rows, fused, lanes in [(3, 1, 1), (1, 1, 1), (1, 0, 4), (2, 1, 16)]:
+    for kind, rows, lanes in [(1, 3, 1), (1, 1, 1), (0, 1, 4), (1, 2, 16)]:
+        m.set_estep_kernel(kind)
         m.set_slot_rows(rows)
-        m.set_ll_fusion(fused)
         m.set_gather_lanes(lanes)
         m.init_seeds(lab)
         it = m.em_iterate(lab, 30, 1e-4)
-        eager = run(im, dev, 30, 2, 0, 1e-4, rows=rows, fused=fused, lanes=lanes)
-        assert np.array_equal(m.get_params(), eager["theta"]), (rows, fused, lanes)
-        assert np.array_equal(m.ll_history(0), eager["hist"]), (rows, fused, lanes)
-        assert np.array_equal(it, eager["iters"]), (rows, fused, lanes)
+        eager = run(im, dev, 30, 2, 0, 1e-4, kind=kind, rows=rows, lanes=lanes)
+        assert np.array_equal(m.get_params(), eager["theta"]), (kind, rows, lanes)
+        assert np.array_equal(m.ll_history(0), eager["hist"]), (kind, rows, lanes)
+        assert np.array_equal(it, eager["iters"]), (kind, rows, lanes)
 
 
 @pytest.mark.parametrize("wpc,lanes", [(1, 16), (4, 16), (1, 4), (2, 4)])
