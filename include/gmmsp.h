@@ -48,6 +48,10 @@ typedef enum gmmsp_status {
   GMMSP_E_INVAL = -1,   /* bad argument: null pointer, non-positive size or constant */
   GMMSP_E_SIZE = -2,    /* sizes that give an empty grid, or workspace too small    */
   GMMSP_E_HIP = -3,     /* a HIP runtime call failed                                */
+  GMMSP_E_NOMEM = -4,   /* host memory for the handle's tables, pinned host memory or
+                           a HIP object could not be allocated (the library allocates
+                           no device memory; a caller's buffers that are too small
+                           give E_SIZE)                                             */
   GMMSP_E_STATE = -5    /* call out of order, or iteration history exhausted        */
 } gmmsp_status;
 

@@ -15,6 +15,7 @@ GMMSP_OK = 0
 GMMSP_E_INVAL = -1
 GMMSP_E_SIZE = -2
 GMMSP_E_HIP = -3
+GMMSP_E_NOMEM = -4
 GMMSP_E_STATE = -5
 THETA_ROW = 13
 THETA_ROW3 = 15

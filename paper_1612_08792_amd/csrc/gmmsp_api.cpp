@@ -35,7 +35,8 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int hip_fail(hipError_t e, const char* what) {
-  return fail(GMMSP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? GMMSP_E_NOMEM : GMMSP_E_HIP, "%s: %s", what,
+              hipGetErrorString(e));
 }
 
 // floor(sqrt(n)) for n >= 0, exact
@@ -268,8 +269,12 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
 
   std::vector<CellDesc> cells;
   std::vector<SpDesc> sps;
-  cells.reserve(L.n_cell);
-  sps.reserve(L.n_sp);
+  try {  // the host tables of the batch; no exception leaves the ABI
+    cells.reserve(L.n_cell);
+    sps.reserve(L.n_sp);
+  } catch (const std::bad_alloc&) {
+    return fail(GMMSP_E_NOMEM, "out of host memory for %d cells", L.n_cell);
+  }
   for (int32_t b = 0; b < n_images; ++b) {
     const ImgDesc& d = descs[b];
     for (int cy = 0; cy < d.ncy; ++cy)
@@ -278,7 +283,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
       for (int kx = 0; kx < d.nx; ++kx) sps.push_back(SpDesc{b, kx, ky, 0});
   }
   gmmsp_handle* h = new (std::nothrow) gmmsp_handle();
-  if (!h) return fail(GMMSP_E_INVAL, "out of host memory");
+  if (!h) return fail(GMMSP_E_NOMEM, "out of host memory");
   char* base = (char*)workspace_dev;
   h->n_img = n_images;
   h->n_pix = L.n_pix;
