@@ -33,11 +33,27 @@ namespace {
 
 constexpr int kQ = 7;  // column phases per slot: 9 x 7 = 63 lanes
 
-// LDS of one wave for J columns per lane and RC rows per chunk.
+// The smallest stride (a multiple of 4 floats, at least `need`) at which the
+// seven column phases' reads of `width` consecutive floats fall in distinct
+// LDS banks (64 banks of 4 bytes).
+constexpr int bank_stride(int need, int width) {
+  for (int s = ((need + 3) / 4) * 4;; s += 4) {
+    bool ok = true;
+    for (int k = 1; k < kQ && ok; ++k) {
+      const int d = (k * s) % 64;
+      if (d < width || 64 - d < width) ok = false;
+    }
+    if (ok) return s;
+  }
+}
+
+// LDS of one wave for J columns per lane and RC rows per chunk.  The e rows
+// of consecutive lanes are 4 x odd floats apart, so that 16 lanes' 16-byte
+// writes fall in distinct banks.
 template <int J, int RC>
 struct SlotLds {
-  static constexpr int kPB = ((RC * J * 3 + 3) / 4) * 4;  // pixel floats per column phase
-  static constexpr int kEB = ((RC * J + 3) / 4) * 4;      // e floats per (slot, phase)
+  static constexpr int kPB = bank_stride(RC * J * 3, 3);  // pixel floats per column phase
+  static constexpr int kEB = ((RC * J + 3) / 8) * 8 + 4;  // e floats per (slot, phase)
   static constexpr int kPix = kQ * kPB;
   static constexpr int kE = (kSlots + 1) * kQ * kEB;       // + the idle lane's row
   static constexpr int kInv = kQ * kEB;
