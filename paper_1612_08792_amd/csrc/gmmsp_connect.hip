@@ -725,12 +725,39 @@ __global__ __launch_bounds__(kT) void k_merge(const ImgDesc* img, int n_seg, con
                 next, tail);
 }
 
-// Large clusters, one wave each: the sources sorted by (size, id) with a
-// bitonic sort in LDS, then visited in order with the wave's lanes sharing the
-// pixels of the source and a butterfly for the nearest neighbour.  The state
-// one visit writes (lane 0) is made visible to the wave before the next visit.
-constexpr int kSortCap = 1024;
-constexpr int kMergeWaves = 4;
+// Large clusters, one wave each, with the cluster's whole merge state in LDS.
+// The sources are sorted by (size, id) with a bitonic sort; each source gets a
+// local index in that order, and so does every large segment adjacent to the
+// cluster (its "external" neighbours), through an LDS table from segment id to
+// local index.  Before the first visit the wave records, for every pixel of
+// every source, the local indices of the segments holding its 4-neighbours
+// (4 entries per pixel); a visit then reads only LDS: the member chain of the
+// source, the entries of the members' pixels, the current owner of each entry
+// (merge-parent walk), the colour means of the source and the owners.  The
+// owner set of a visit is exactly the set of current owners of the 4-neighbours
+// of every pixel merged into the source, so the decision is the one of the
+// sequential procedure.  A cluster that does not fit (members and externals,
+// or neighbour entries) runs on one lane with the state in memory.
+constexpr int kLCap = 768;     // members + external neighbours held in LDS
+constexpr int kLSort = 1024;   // bitonic sort width (power of two >= kLCap)
+constexpr int kLAdj = 8192;    // neighbour entries: 4 per member pixel
+constexpr int kLHash = 2048;   // segment id -> local index table
+constexpr int kLWaves = 2;     // waves (clusters) per block
+constexpr unsigned short kNone = 0xFFFF;
+
+struct ClusterLds {
+  unsigned long long key[kLSort];
+  double mean[kLCap][3];
+  int gid[kLCap];                // segment id of each local index
+  int sz[kLCap];                 // current size of each member
+  int pref[kLCap + 1];           // first pixel of each member, in member order
+  int cum[kLCap + 1];            // entry offsets along the chain of a visit
+  int hkey[kLHash];
+  short hval[kLHash];
+  short mp[kLCap], nx[kLCap], tl[kLCap], chain[kLCap];
+  unsigned short adj[kLAdj];
+  int n_ext, overflow, n_chain;
+};
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -738,75 +765,224 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(64 * kMergeWaves) void k_merge_big(
+__device__ __forceinline__ int hash_slot(int id) {
+  return (int)(((unsigned)id * 2654435761u) >> 21) & (kLHash - 1);
+}
+
+// local index of segment t, inserting it as an external neighbour when new
+__device__ int lds_index(ClusterLds& S, int t) {
+  int e = hash_slot(t);
+  for (int probe = 0; probe < kLHash; ++probe, e = (e + 1) & (kLHash - 1)) {
+    const int k = atomicCAS(&S.hkey[e], -1, t);
+    if (k == -1) {  // this lane inserted t: a new external slot
+      const int slot = atomicAdd(&S.n_ext, 1);
+      S.hval[e] = (short)(slot < kLCap ? slot : -1);
+      if (slot < kLCap) S.gid[slot] = t;
+      else S.overflow = 1;
+    }
+    if (k == -1 || k == t) return e;  // the value is read once every lane has stored
+  }
+  S.overflow = 1;
+  return -1;
+}
+
+__device__ __forceinline__ int lds_owner(const ClusterLds& S, int n, int x) {
+  while (x < n && S.mp[x] != x) x = S.mp[x];
+  return x;
+}
+
+__global__ __launch_bounds__(64 * kLWaves) void k_merge_big(
     const ImgDesc* img, const int* seg_img, const int* size0, const int* ccnt, const int* coff,
     int* list, const int* poff, const int* plist, const int* segid, const double* mean, int* size,
     int* mpar, int* next, int* tail, const int* big, const int* n_big) {
-  __shared__ unsigned long long keys[kMergeWaves][kSortCap];
+  __shared__ ClusterLds lds[kLWaves];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned long long* kw = keys[wv];
+  ClusterLds& S = lds[wv];
   const int nbig = *n_big;
-  for (int c = blockIdx.x * kMergeWaves + wv; c < nbig; c += gridDim.x * kMergeWaves) {
+  for (int c = blockIdx.x * kLWaves + wv; c < nbig; c += gridDim.x * kLWaves) {
     const int r = big[c];
     const int n = ccnt[r];
-    if (n > kSortCap) {  // too large for the LDS sort: one lane runs it all
+    const int* v = list + coff[r];
+    const ImgDesc& I = img[seg_img[r]];
+    const int W = I.W, H = I.H;
+    const int off = (int)I.pix_off;
+    const int64_t desired = (int64_t)I.vx * I.vy;
+    bool fits = n <= kLCap;
+    if (fits) {
+      // sort the sources by (size, id)
+      int P = 1;
+      while (P < n) P <<= 1;
+      for (int i = lane; i < P; i += 64)
+        S.key[i] = i < n ? ((unsigned long long)size0[v[i]] << 32) | (unsigned)v[i] : ~0ull;
+      for (int e = lane; e < kLHash; e += 64) {
+        S.hkey[e] = -1;
+        S.hval[e] = -1;
+      }
+      if (lane == 0) {
+        S.n_ext = n;
+        S.overflow = 0;
+      }
+      wave_sync_lds();
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = lane; i < P; i += 64) {
+            const int l = i ^ j;
+            if (l > i) {
+              const unsigned long long a = S.key[i], b = S.key[l];
+              if ((a > b) == ((i & k) == 0)) {
+                S.key[i] = b;
+                S.key[l] = a;
+              }
+            }
+          }
+          wave_sync_lds();
+        }
+      }
+      // members: ids, sizes, chains, means, table entries
+      for (int q = lane; q < n; q += 64) {
+        const int g = (int)(unsigned)(S.key[q] & 0xFFFFFFFFull);
+        S.gid[q] = g;
+        S.sz[q] = size0[g];
+        S.mp[q] = (short)q;
+        S.nx[q] = -1;
+        S.tl[q] = (short)q;
+        int e = hash_slot(g);
+        while (atomicCAS(&S.hkey[e], -1, g) != -1) e = (e + 1) & (kLHash - 1);
+        S.hval[e] = (short)q;
+      }
+      // first pixel of each member: per-lane chunk sums, then a wave scan
+      const int chunk = (n + 63) / 64;
+      const int q0 = min(n, lane * chunk), q1 = min(n, q0 + chunk);
+      int part = 0;
+      for (int q = q0; q < q1; ++q) part += size0[(int)(unsigned)(S.key[q] & 0xFFFFFFFFull)];
+      int incl = part;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      int run = incl - part;
+      for (int q = q0; q < q1; ++q) {
+        S.pref[q] = run;
+        run += size0[(int)(unsigned)(S.key[q] & 0xFFFFFFFFull)];
+      }
+      const int total = __shfl(incl, 63, 64);
+      if (lane == 0) S.pref[n] = total;
+      wave_sync_lds();
+      fits = 4 * total <= kLAdj;
+    }
+    if (fits) {
+      // the 4-neighbour entries of every member pixel (up, down, left, right)
+      const int total = S.pref[n];
+      for (int u = lane; u < total; u += 64) {
+        int lo = 0, hi = n;  // the member q with pref[q] <= u < pref[q + 1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (S.pref[mid] <= u) lo = mid;
+          else hi = mid;
+        }
+        const int g = S.gid[lo];
+        const int j = plist[poff[g] + (u - S.pref[lo])] - off;
+        const int x = j % W, y = j / W;
+        int t[4];
+        t[0] = y > 0 ? segid[off + j - W] : g;
+        t[1] = y + 1 < H ? segid[off + j + W] : g;
+        t[2] = x > 0 ? segid[off + j - 1] : g;
+        t[3] = x + 1 < W ? segid[off + j + 1] : g;
+        int e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = t[k] != g ? lds_index(S, t[k]) : -1;
+        wave_sync_lds();  // every inserting lane has stored its value
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int idx = e[k] >= 0 ? S.hval[e[k]] : -1;
+          S.adj[4 * u + k] = idx >= 0 ? (unsigned short)idx : kNone;
+        }
+      }
+      wave_sync_lds();
+      // colour means of the members and the external neighbours
+      const int nl = min(S.n_ext, kLCap);
+      for (int i = lane; i < nl; i += 64) {
+        const double* m = mean + 3 * (int64_t)S.gid[i];
+        S.mean[i][0] = m[0];
+        S.mean[i][1] = m[1];
+        S.mean[i][2] = m[2];
+      }
+      wave_sync_lds();
+      fits = S.overflow == 0;
+    }
+    if (!fits) {  // the state in memory, one lane
       if (lane == 0)
         merge_cluster(img, r, seg_img, size0, ccnt, coff, list, poff, plist, segid, mean, size,
                       mpar, next, tail);
       continue;
     }
-    const int* v = list + coff[r];
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = lane; i < P; i += 64)
-      kw[i] = i < n ? ((unsigned long long)size0[v[i]] << 32) | (unsigned)v[i] : ~0ull;
-    wave_sync_lds();
-    for (int k = 2; k <= P; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = lane; i < P; i += 64) {
-          const int l = i ^ j;
-          if (l > i) {
-            const unsigned long long a = kw[i], b = kw[l];
-            if ((a > b) == ((i & k) == 0)) {
-              kw[i] = b;
-              kw[l] = a;
-            }
-          }
-        }
-        wave_sync_lds();
-      }
-    }
-    const ImgDesc& I = img[seg_img[r]];
-    const int W = I.W, H = I.H;
-    const int off = (int)I.pix_off;
-    const int64_t desired = (int64_t)I.vx * I.vy;
+    // the visits, in (size, id) order
     for (int q = 0; q < n; ++q) {
-      const int s = (int)(unsigned)(kw[q] & 0xFFFFFFFFull);
-      if (4LL * ld_dev(size + s) >= desired) continue;
-      const double* ms = mean + 3 * (int64_t)s;
-      int best = -1;
+      if (4LL * S.sz[q] >= desired) continue;
+      if (lane == 0) {  // the members merged into q so far, and their entry offsets
+        int nc = 0, acc = 0;
+        for (int m = q; m >= 0; m = S.nx[m]) {
+          S.chain[nc] = (short)m;
+          S.cum[nc] = acc;
+          acc += 4 * (S.pref[m + 1] - S.pref[m]);
+          ++nc;
+        }
+        S.cum[nc] = acc;
+        S.n_chain = nc;
+      }
+      wave_sync_lds();
+      const int nc = S.n_chain, T = S.cum[nc];
+      const double ms[3] = {S.mean[q][0], S.mean[q][1], S.mean[q][2]};
+      int best = -1, bidx = -1;
       double bd = 0.0;
-      for (int m = s; m >= 0; m = ld_dev(next + m)) {
-        const int p0 = poff[m], np = size0[m];
-        for (int u = lane; u < np; u += 64)
-          scan_pixel(plist[p0 + u] - off, W, H, off, s, ms, segid, mpar, mean, best, bd);
+      for (int u = lane; u < T; u += 64) {
+        int lo = 0, hi = nc;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (S.cum[mid] <= u) lo = mid;
+          else hi = mid;
+        }
+        const int m = S.chain[lo];
+        const unsigned short a = S.adj[4 * S.pref[m] + (u - S.cum[lo])];
+        if (a == kNone) continue;
+        const int o = lds_owner(S, n, a);
+        if (o == q) continue;
+        const double d = colour_dist2(ms, S.mean[o]);
+        const int go = S.gid[o];
+        if (best < 0 || d < bd || (d == bd && go < best)) {
+          best = go;
+          bidx = o;
+          bd = d;
+        }
       }
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
         const double od = __shfl_xor(bd, o, 64);
         const int ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bidx, o, 64);
         if (ob >= 0 && (best < 0 || od < bd || (od == bd && ob < best))) {
           best = ob;
+          bidx = oi;
           bd = od;
         }
       }
       if (best < 0) continue;  // every lane holds the same result
-      if (lane == 0) merge_into(img, seg_img, size0, s, best, size, mpar, next, tail);
-      // lane 0's stores complete before any lane's next (L2-served) reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if (lane == 0) {
+        S.mp[q] = (short)bidx;
+        if (bidx < n) {  // into a member: size and member chain move over
+          S.sz[bidx] += S.sz[q];
+          S.nx[S.tl[bidx]] = (short)q;
+          S.tl[bidx] = S.tl[q];
+        }
+        S.sz[q] = 0;
+      }
+      wave_sync_lds();
     }
+    // merge parents back to memory, as segment ids (a large destination's size
+    // is read by no decision and no output)
+    for (int q = lane; q < n; q += 64) mpar[S.gid[q]] = S.gid[S.mp[q]];
+    wave_sync_lds();  // the table and arrays are rewritten by the next cluster
   }
 }
 
@@ -936,7 +1112,7 @@ hipError_t conn_launch_merge(const ConnPtrs& C, const ImgDesc* img, int n_img, i
                      C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
                      reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail,
                      C.scan, C.n_big);
-  hipLaunchKernelGGL(k_merge_big, dim3(1024), dim3(64 * kMergeWaves), 0, s, img, C.seg_img,
+  hipLaunchKernelGGL(k_merge_big, dim3(1024), dim3(64 * kLWaves), 0, s, img, C.seg_img,
                      C.size0, C.ccnt, C.coff, C.list, C.poff, C.par, C.segid,
                      reinterpret_cast<const double*>(C.colsum), C.size, C.mpar, C.next, C.tail,
                      C.scan, C.n_big);

@@ -62,7 +62,8 @@ def main():
         srgb8_to_lab(rgb, lab)
         mark()
         flat = lab.reshape(-1)
-        warmstart.warm_start(m, flat, params, train_warmstart.MASK)
+        # the guarded start: the grid seeds wherever they give the higher L(theta^0)
+        warmstart.warm_start(m, flat, params, warmstart.APPLY_MASK, guard=True)
         mark()
         it = m.em_iterate(flat, 200, 1e-5)
         mark()

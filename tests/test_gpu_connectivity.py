@@ -81,6 +81,50 @@ def test_fragmented_uneven_batch(dev):
     check_exact(dev, items, 9)
 
 
+def small_cluster_sizes(labels, v):
+    """Sizes (in segments) and pixel counts of the clusters of 4-adjacent small
+    segments, from scipy's component labelling on the CPU."""
+    from scipy import ndimage
+    seg = np.full(labels.shape, -1, np.int64)
+    n = 0
+    for val in np.unique(labels):
+        comp, k = ndimage.label(labels == val)
+        seg[comp > 0] = comp[comp > 0] - 1 + n
+        n += k
+    size = np.bincount(seg.ravel(), minlength=n)
+    small = 4 * size < v * v
+    a = np.concatenate([seg[:, :-1].ravel(), seg[:-1, :].ravel()])
+    b = np.concatenate([seg[:, 1:].ravel(), seg[1:, :].ravel()])
+    keep = (a != b) & small[a] & small[b]
+    g = coo_matrix((np.ones(keep.sum()), (a[keep], b[keep])), shape=(n, n))
+    _, cl = connected_components(g, directed=False)
+    members = np.bincount(cl[small])
+    pixels = np.bincount(cl[small], weights=size[small])
+    return members[members > 0], pixels[members > 0]
+
+
+def test_large_clusters_bit_exact(dev):
+    """Clusters of more than 16 small segments run one wave each with their
+    state in LDS (up to 768 members and external neighbours, 2048 member
+    pixels); larger ones on one lane with the state in memory.  Both against
+    the oracle, bit for bit: two fragment fields (clusters of 17 to 695
+    segments) and 25 adjacent 30 x 30 blocks under v = 64 (one cluster of 25
+    segments and 22 500 pixels, too many pixels for LDS)."""
+    frag = [fragmented(31, 200, 240, 16, 0.5), fragmented(34, 256, 256, 16, 0.55)]
+    sizes = [small_cluster_sizes(l, 16) for l, _ in frag]
+    members = np.concatenate([m for m, _ in sizes])
+    pixels = np.concatenate([p for _, p in sizes])
+    lds = (members > 16) & (members <= 768) & (pixels <= 2048)
+    assert lds.sum() >= 100 and members[lds].max() >= 600, (lds.sum(), members.max())
+    check_exact(dev, frag, 16)
+    H = W = 150
+    blocks = (np.arange(H)[:, None] // 30) * 10 + (np.arange(W)[None, :] // 30)
+    m, p = small_cluster_sizes(blocks, 64)
+    assert list(m) == [25] and p[0] == 22500
+    rng = np.random.default_rng(5)
+    check_exact(dev, [(blocks, rng.uniform(0, 100, (H, W, 3)).astype(np.float32))], 64)
+
+
 def test_checkerboard_is_one_cluster(dev):
     # every pixel is its own segment, all small, all in one cluster
     H, W = 40, 48
