@@ -222,7 +222,8 @@ int gmmsp_get_slot_rows(const gmmsp_handle* h, int32_t* rows);
 
 /* Autotuner of the statistics pass: for each candidate schedule, `passes` em
  * passes (statistics, L, gather; after three untimed) from the grid
- * initialisation, timed with HIP events on `stream`.  Candidates, in order of
+ * initialisation, timed with HIP events on `stream`, in two rounds over all
+ * candidates (each candidate's faster round counts).  Candidates, in order of
  * preference: the slot-lane pass (kind 1) with each built rows-per-chunk value,
  * largest first, then the pixel-lane pass (kind 0); 1, 2 and 4 waves per cell
  * each.  A later candidate is kept only if it is more than 3 % faster than the

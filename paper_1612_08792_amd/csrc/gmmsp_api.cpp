@@ -313,6 +313,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   for (const ImgDesc& d : descs) max_vx = std::max(max_vx, d.vx);
   P.estep = 0;
   if (P.cov_mode == 0 && slots_shape(max_vx, &P.slot_j, &P.slot_rc)) P.estep = 1;
+  P.slot_rc_max = P.slot_rc;
 
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync((void*)P.img, descs.data(), sizeof(ImgDesc) * n_images,
@@ -742,33 +743,42 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   }
   if (ms_host)
     for (int c = 0; c < GMMSP_TUNE_CANDIDATES; ++c) ms_host[c] = -1.0;
-  double best = 0.0;
-  Cand pick = cands[0];
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
-    h->P.estep = cands[c].kind;
-    if (h->P.slot_j) h->P.slot_rc = cands[c].rc;
-    h->P.wpc = cands[c].wpc;
-    e = launch_reset_state(h->P, s);
-    if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
-    double tot = 0.0;
-    // kTuneWarm untimed passes (the first passes from the grid seeds run
-    // slower than later ones), then `passes` timed ones: whole em passes, as
-    // the waves per cell also set the work of the gather
-    for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
-      e = hipEventRecord(a, s);
-      if (e == hipSuccess) e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      if (i >= kTuneWarm) tot += ms;
+  // two rounds over the candidates, each candidate's faster round counts: the
+  // first candidates of a round would otherwise also pay for the GPU's clock
+  // ramp at the start
+  std::vector<double> tmin(cands.size(), 0.0);
+  for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+    for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+      h->P.estep = cands[c].kind;
+      if (h->P.slot_j) h->P.slot_rc = cands[c].rc;
+      h->P.wpc = cands[c].wpc;
+      e = launch_reset_state(h->P, s);
+      if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+      double tot = 0.0;
+      // kTuneWarm untimed passes (the first passes from the grid seeds run
+      // slower than later ones), then `passes` timed ones: whole em passes, as
+      // the waves per cell also set the work of the gather
+      for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (i >= kTuneWarm) tot += ms;
+      }
+      if (round == 0 || tot < tmin[c]) tmin[c] = tot;
     }
-    if (ms_host) ms_host[cands[c].idx] = tot;
-    if (c == 0 || tot < kTuneMargin * best) {
-      best = tot;
+  }
+  double best = 0.0;
+  Cand pick = cands[0];
+  for (size_t c = 0; c < cands.size(); ++c) {
+    if (ms_host) ms_host[cands[c].idx] = tmin[c];
+    if (c == 0 || tmin[c] < kTuneMargin * best) {
+      best = tmin[c];
       pick = cands[c];
     }
   }

@@ -114,6 +114,7 @@ struct DevPtrs {
                             // lane (k_cells), 1 one candidate slot per lane (k_slots,
                             // gmmsp_slots.hip; its colour statistics are whitened)
   int32_t slot_j, slot_rc;  // k_slots shape: columns per lane, rows per chunk
+  int32_t slot_rc_max;      // the largest rows per chunk of this batch's shape
 };
 
 // How a per-image log-likelihood L(theta^t) is committed: LL_EM appends it to
@@ -182,6 +183,9 @@ hipError_t launch_export_candidates(const DevPtrs& P, int32_t* cand, hipStream_t
 int slots_shape(int max_w, int* J, int* RC);
 int slots_rows(int J, int max_rc, int* rows, int cap);
 hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s);
+// the slot-lane pass's log-likelihood terms alone (no statistics), one wave per
+// cell: per-cell L terms in llp set 0
+hipError_t launch_ll_slots(const DevPtrs& P, const float* lab, hipStream_t s);
 
 // The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
 // 2 responsibilities, 3 candidates.

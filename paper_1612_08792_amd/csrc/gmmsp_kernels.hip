@@ -803,11 +803,19 @@ hipError_t launch_seed_fallback(const DevPtrs& P, const float* lab, hipStream_t 
 }
 
 hipError_t launch_ll_eval(const DevPtrs& P, const float* lab, int to_seed, hipStream_t s) {
-  // the statistics pass evaluates L(theta) per cell wave (its partials are
-  // scratch until the next pass); images marked done are evaluated too
+  // L(theta) per cell wave: the slot-lane pass without its statistics, else the
+  // statistics pass (its partials are scratch until the next pass); images
+  // marked done are evaluated too
+  const int mode = to_seed ? LL_SEED : LL_FINAL;
   hipError_t e = launch_reset_state(P, s);
-  if (e == hipSuccess) e = launch_estep_ll(P, lab, to_seed ? LL_SEED : LL_FINAL, 0.0, s);
-  return e;
+  if (e != hipSuccess) return e;
+  if (P.cov_mode == 0 && P.slot_j) {
+    e = launch_ll_slots(P, lab, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ll_reduce, dim3(P.n_img), dim3(kLLThreads), 0, s, P, 0.0, mode, 1);
+    return hipGetLastError();
+  }
+  return launch_estep_ll(P, lab, mode, 0.0, s);
 }
 
 hipError_t launch_set_params(const DevPtrs& P, const double* rows, hipStream_t s) {

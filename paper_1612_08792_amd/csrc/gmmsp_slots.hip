@@ -78,7 +78,9 @@ __device__ __forceinline__ float vreg(float x) {
 
 }  // namespace
 
-template <int J, int RC, int WPC>
+// STATS false: only the log-likelihood terms (phase 3, the partials and the
+// shifted e of the fallback are skipped), for evaluating L(theta) alone.
+template <int J, int RC, int WPC, bool STATS = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
     DevPtrs P, const float* __restrict__ lab) {
   // products are rounded where written: every shape of the kernel rounds alike
@@ -252,23 +254,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           SH[p_e] = INFINITY;  // not shifted
         }
       }
-      wave_sync();
-      const float* sh = SH + q * LL::kEB;
+      if constexpr (STATS) {
+        wave_sync();
+        const float* sh = SH + q * LL::kEB;
 #pragma unroll
-      for (int i = 0; i < RC; ++i)
+        for (int i = 0; i < RC; ++i)
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-          const float m = sh[i * J + j];
-          if (m != INFINITY) e[i][j] = __builtin_amdgcn_exp2f(log_density(i, j) - m);
-        }
+          for (int j = 0; j < J; ++j) {
+            const float m = sh[i * J + j];
+            if (m != INFINITY) e[i][j] = __builtin_amdgcn_exp2f(log_density(i, j) - m);
+          }
+      }
     }
     if (pv) {
-      INV[p_e] = inv;
+      if constexpr (STATS) INV[p_e] = inv;
       // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
       // integer-valued FP64 sums are exact, so L does not depend on how pixels
       // are grouped into chunks and lanes
       ll64 += rint((double)lg * 0x1p22);
     }
+    if constexpr (!STATS) continue;
     wave_sync();
     // phase 3: R = e / sum and the slot's sufficient statistics
     {
@@ -298,45 +303,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   }
 
-  // this lane's statistics of its slot over its columns: spatial moments
-  // about the cell origin from the per-column sums
-  float st[kStats];
-  st[S_N] = 0.f;
-  st[S_X] = 0.f;
-  st[S_Y] = 0.f;
-  st[S_XX] = 0.f;
-  st[S_XY] = 0.f;
-  st[S_YY] = 0.f;
+  if constexpr (STATS) {
+    // this lane's statistics of its slot over its columns: spatial moments
+    // about the cell origin from the per-column sums
+    float st[kStats];
+    st[S_N] = 0.f;
+    st[S_X] = 0.f;
+    st[S_Y] = 0.f;
+    st[S_XX] = 0.f;
+    st[S_XY] = 0.f;
+    st[S_YY] = 0.f;
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const float c = (float)(q + kQ * j);
-    st[S_N] += Nj[j];
-    st[S_X] = fmaf(c, Nj[j], st[S_X]);
-    st[S_XX] = fmaf(c * c, Nj[j], st[S_XX]);
-    st[S_Y] += Mj[j];
-    st[S_XY] = fmaf(c, Mj[j], st[S_XY]);
-    st[S_YY] += Qj[j];
-  }
-  // colour moments in the whitened coordinates of the slot's record
-  st[S_L] = Sw;
-  st[S_A] = Su1;
-  st[S_B] = Su2;
-  st[S_LL] = Sww;
-  st[S_AA] = S11;
-  st[S_AB] = S12;
-  st[S_BB] = S22;
-  wave_sync();  // the last chunk's reads of E, INV and SH are done
+    for (int j = 0; j < J; ++j) {
+      const float c = (float)(q + kQ * j);
+      st[S_N] += Nj[j];
+      st[S_X] = fmaf(c, Nj[j], st[S_X]);
+      st[S_XX] = fmaf(c * c, Nj[j], st[S_XX]);
+      st[S_Y] += Mj[j];
+      st[S_XY] = fmaf(c, Mj[j], st[S_XY]);
+      st[S_YY] += Qj[j];
+    }
+    // colour moments in the whitened coordinates of the slot's record
+    st[S_L] = Sw;
+    st[S_A] = Su1;
+    st[S_B] = Su2;
+    st[S_LL] = Sww;
+    st[S_AA] = S11;
+    st[S_AB] = S12;
+    st[S_BB] = S22;
+    wave_sync();  // the last chunk's reads of E, INV and SH are done
 #pragma unroll
-  for (int t = 0; t < kStats; ++t) RED[lane * kStats + t] = st[t];
-  wave_sync();
-  // the cell's totals: the seven lanes of each slot in ascending phase order
-  float* part = reinterpret_cast<float*>(P.part) + ((size_t)sub * P.n_cell + cell) * kPartStride;
-  for (int o = lane; o < kSlots * kStats; o += 64) {
-    const int so = o / kStats, t = o - so * kStats;
-    float a = 0.f;
+    for (int t = 0; t < kStats; ++t) RED[lane * kStats + t] = st[t];
+    wave_sync();
+    // the cell's totals: the seven lanes of each slot in ascending phase order
+    float* part = reinterpret_cast<float*>(P.part) + ((size_t)sub * P.n_cell + cell) * kPartStride;
+    for (int o = lane; o < kSlots * kStats; o += 64) {
+      const int so = o / kStats, t = o - so * kStats;
+      float a = 0.f;
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) a += RED[(so * kQ + k) * kStats + t];
-    part[o] = a;
+      for (int k = 0; k < kQ; ++k) a += RED[(so * kQ + k) * kStats + t];
+      part[o] = a;
+    }
   }
   // cell log-likelihood: ln 2 (sum of log2 terms) + pixels x ln(cmax); the
   // integer-valued sums stay exact
@@ -391,6 +398,31 @@ int slots_rows(int J, int max_rc, int* rows, int cap) {
   for (int i = 0; i < 3 && n < cap; ++i)
     if (kBuilt[J - 1][i] > 0 && kBuilt[J - 1][i] <= max_rc) rows[n++] = kBuilt[J - 1][i];
   return n;
+}
+
+namespace {
+template <int J, int RC>
+hipError_t launch_ll_jrc(const DevPtrs& P, const float* lab, hipStream_t s) {
+  const dim3 grid((unsigned)(((size_t)P.n_cell + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL((k_slots<J, RC, 1, false>), grid, dim3(256), 0, s, P, lab);
+  return hipGetLastError();
+}
+}  // namespace
+
+// The log-likelihood terms alone, one wave per cell (llp set 0), with the
+// largest rows-per-chunk value of the batch's shape.
+hipError_t launch_ll_slots(const DevPtrs& P, const float* lab, hipStream_t s) {
+  switch (P.slot_j) {
+    case 1: return launch_ll_jrc<1, 8>(P, lab, s);
+    case 2: return launch_ll_jrc<2, 4>(P, lab, s);
+    case 3: return launch_ll_jrc<3, 3>(P, lab, s);
+    case 4: return launch_ll_jrc<4, 2>(P, lab, s);
+    case 5: return P.slot_rc_max == 2 ? launch_ll_jrc<5, 2>(P, lab, s) : launch_ll_jrc<5, 1>(P, lab, s);
+    case 6: return launch_ll_jrc<6, 1>(P, lab, s);
+    case 7: return launch_ll_jrc<7, 1>(P, lab, s);
+    case 8: return launch_ll_jrc<8, 1>(P, lab, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s) {
