@@ -249,14 +249,14 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
 int gmmsp_set_gather_lanes(gmmsp_handle* h, int32_t lanes_per_superpixel);
 int gmmsp_get_gather_lanes(const gmmsp_handle* h, int32_t* lanes_per_superpixel);
 
-/* Autotuner of the gather: for 1, 4 and 16 lanes per superpixel, one
- * statistics pass from the grid initialisation, then `passes` gathers (after
- * one untimed) timed with HIP events on `stream`; more lanes are kept only if
+/* Autotuner of the gather: for 1, 4 and 16 lanes per superpixel, `passes`
+ * whole em passes (after three untimed) from the grid initialisation with the
+ * statistics-pass schedule in effect, timed with HIP events on `stream`, in two
+ * rounds (each candidate's faster round counts); more lanes are kept only if
  * more than 3 % faster than the best with fewer.  Leaves the handle
- * initialised by gmmsp_init_seeds.  Run
- * it after gmmsp_autotune (it gathers the statistics of the chosen waves per
- * cell).  ms_host (nullable, 3 doubles, in the order 1, 4, 16): the measured
- * times (-1 for a schedule not timed). */
+ * initialised by gmmsp_init_seeds.  Run it after gmmsp_autotune.  ms_host
+ * (nullable, 3 doubles, in the order 1, 4, 16): the measured times (-1 for a
+ * schedule not timed). */
 int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
                           double* ms_host, int32_t* chosen, void* stream);
 

@@ -805,30 +805,35 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
   const int n_cand = h->P.cov_mode != 0 ? 1 : 3;
   if (ms_host)
     for (int c = 0; c < 3; ++c) ms_host[c] = -1.0;
-  double best = 0.0;
-  int32_t pick = 1;
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  for (int c = 0; c < n_cand && e == hipSuccess; ++c) {
-    h->P.glanes = cand[c];
-    // statistics of one pass from the grid seeds, then the gather timed on them
-    e = launch_reset_state(h->P, s);
-    if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
-    if (e == hipSuccess) e = launch_estep_stats(h->P, lab_dev, s);
-    double tot = 0.0;
-    for (int32_t i = 0; i <= passes && e == hipSuccess; ++i) {
-      e = hipEventRecord(a, s);
-      if (e == hipSuccess) e = launch_finalize(h->P, s);
-      if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      if (i > 0) tot += ms;  // the first launch is untimed
+  // whole em passes with each gather, two rounds, each candidate's faster counts
+  double tmin[3] = {0.0, 0.0, 0.0};
+  for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+    for (int c = 0; c < n_cand && e == hipSuccess; ++c) {
+      h->P.glanes = cand[c];
+      e = launch_reset_state(h->P, s);
+      if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+      double tot = 0.0;
+      for (int32_t i = 0; i < kTuneWarm + passes && e == hipSuccess; ++i) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (i >= kTuneWarm) tot += ms;
+      }
+      if (round == 0 || tot < tmin[c]) tmin[c] = tot;
     }
-    if (ms_host) ms_host[c] = tot;
-    if (c == 0 || tot < kTuneMargin * best) {
-      best = tot;
+  }
+  double best = 0.0;
+  int32_t pick = 1;
+  for (int c = 0; c < n_cand; ++c) {
+    if (ms_host) ms_host[c] = tmin[c];
+    if (c == 0 || tmin[c] < kTuneMargin * best) {
+      best = tmin[c];
       pick = cand[c];
     }
   }
