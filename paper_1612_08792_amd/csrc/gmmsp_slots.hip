@@ -192,14 +192,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         tu2[i][j] = fmaf(A22, Bv, O4);
       }
     }
-    // l = C - t1^2 - t2^2 - w^2 - u1^2 - u2^2 with t1 = L11 x + L12 y + O1
+    // l = C - t1^2 - t2^2 - w^2 - u1^2 - u2^2 with t1 = L11 x + L12 y + O1,
+    // each square taken off the running value by one fused multiply-add
     auto log_density = [&](int i, int j) {
       const float t1 = fmaf(L12, rrv[i], ax[j]);
-      float qq = t1 * t1;
-      qq = fmaf(tw[i][j], tw[i][j], qq);
-      qq = fmaf(tu1[i][j], tu1[i][j], qq);
-      qq = fmaf(tu2[i][j], tu2[i][j], qq);
-      return cr[i] - qq;
+      float l = fmaf(-t1, t1, cr[i]);
+      l = fmaf(-tw[i][j], tw[i][j], l);
+      l = fmaf(-tu1[i][j], tu1[i][j], l);
+      return fmaf(-tu2[i][j], tu2[i][j], l);
     };
 #pragma unroll
     for (int i = 0; i < RC; ++i)
@@ -270,8 +270,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       if constexpr (STATS) INV[p_e] = inv;
       // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
       // integer-valued FP64 sums are exact, so L does not depend on how pixels
-      // are grouped into chunks and lanes
-      ll64 += rint((double)lg * 0x1p22);
+      // are grouped into chunks and lanes.  lg * 2^22 is exact in FP32, so
+      // rounding it there equals rounding it in FP64.
+      ll64 += (double)rintf(lg * 0x1p22f);
     }
     if constexpr (!STATS) continue;
     wave_sync();
