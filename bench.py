@@ -466,6 +466,7 @@ def main():
             side.append({k: r[k] for k in ("workload", "images", "pixels", "T",
                                            "mpix_per_s_per_iteration", "ms_per_iteration",
                                            "ms_per_iteration_eager", "ms_per_iteration_graph",
+                                           "ms_per_iteration_persistent", "fastest_form",
                                            "estep_ms_per_launch", "frac_of_157_3", "schedule")})
             log(f"side workload {c}: {side[-1]}")
         out["side_workloads"] = side

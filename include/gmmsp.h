@@ -157,10 +157,15 @@ int gmmsp_get_params(gmmsp_handle* h, double* theta_host, void* stream);
  * (the paper's fixed T).  Images that have stopped are skipped by every kernel.
  * A pass is three launches (statistics, L with the stop rule, gather), or two
  * with rel_tol <= 0, where nothing in the pass waits for L and the gather's
- * launch also forms it (the same fixed-order sum either way).
- * Calls accumulate: a second call continues from the current theta.
+ * launch also forms it (the same fixed-order sum either way); with the
+ * persistent flag (gmmsp_set_persistent) and rel_tol <= 0, all passes are one
+ * cooperative launch.  Calls accumulate: a second call continues from the
+ * current theta; E_STATE, before any launch, for a call that could take an
+ * image past 4096 passes since the last initialisation.
  * iters_host (nullable, n_images int32): M-steps applied per image since the
- * last initialisation.  Synchronises `stream`. */
+ * last initialisation.  Synchronises `stream` at the end (and before the
+ * passes only when the pass count must be read to check the 4096 cap, or with
+ * kernel timing on). */
 int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters,
                      double rel_tol, int32_t* iters_host, void* stream);
 
@@ -267,6 +272,39 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
  * remainder of max_iters runs as single launches.  0 (default) turns it off.
  * Not used while kernel timing is enabled. */
 int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes);
+
+/* Persistent T-mode passes (Algorithm 1 without the stop rule): with on = 1,
+ * gmmsp_em_iterate with rel_tol <= 0 runs all max_iters passes in one
+ * cooperative launch when the statistics pass is the slot-lane kind (kind 1):
+ * each pass is the statistics pass over every cell, a grid-wide barrier, the
+ * gather of every superpixel and L(theta^t) of every image, and a barrier.
+ * The grid holds at most as many blocks as the GPU keeps resident; every
+ * work item runs the per-pass kernels' code, so the passes equal the per-pass
+ * launches with the same schedule bit for bit.  Calls with the stop rule, with
+ * kind 0, or with kernel timing enabled keep the per-pass launches.  Uses the
+ * handle's workspace (its barrier and a device copy of the schedule) and
+ * waits for the launch before returning; E_STATE if a barrier wait ran out
+ * (about 2 s; the passes are then incomplete).  0 (default) turns it off;
+ * E_INVAL for 1 when the batch has no slot-lane pass. */
+int gmmsp_set_persistent(gmmsp_handle* h, int32_t on);
+int gmmsp_get_persistent(const gmmsp_handle* h, int32_t* on);
+
+/* Autotuner of the launch form of T-mode passes: `passes` passes (after three
+ * untimed) from the grid initialisation as per-pass launches with the schedule
+ * in effect, against the persistent launch of the slot-lane pass with each
+ * built rows-per-chunk value (largest first; waves per cell and gather lanes
+ * as in effect), each timed on the host clock from its first launch to the
+ * end of its last pass on `stream` (what the launch form changes is mostly
+ * host launch cost), in two rounds (each candidate's faster round counts).  The persistent form is kept only if more
+ * than 3 % faster than the per-pass launches; it then sets kind 1, its rows
+ * value and the persistent flag, else it leaves the schedule and clears the
+ * flag.  Run it after gmmsp_autotune and gmmsp_autotune_gather.  Leaves the
+ * handle initialised by gmmsp_init_seeds; *chosen = the flag.  ms_host
+ * (nullable, 4 doubles): per-pass launches, then the persistent launch with
+ * the rows values largest first (-1 where not timed, e.g. every persistent
+ * entry for a batch without a slot-lane pass). */
+int gmmsp_autotune_persistent(gmmsp_handle* h, const float* lab_dev, int32_t passes,
+                              double* ms_host, int32_t* chosen, void* stream);
 
 /* Kernel timing for roofline reporting.  While enabled, gmmsp_em_iterate
  * brackets every launch of the E-step/statistics kernel with HIP events on the

@@ -74,6 +74,10 @@ _SIGS = {
     "gmmsp_autotune_gather": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_int32),
                                       c_void_p]),
     "gmmsp_set_graph_passes": (c_int, [c_void_p, c_int32]),
+    "gmmsp_set_persistent": (c_int, [c_void_p, c_int32]),
+    "gmmsp_get_persistent": (c_int, [c_void_p, POINTER(c_int32)]),
+    "gmmsp_autotune_persistent": (c_int, [c_void_p, c_void_p, c_int32, c_void_p,
+                                          POINTER(c_int32), c_void_p]),
     "gmmsp_profile_enable": (c_int, [c_void_p, c_int32]),
     "gmmsp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
                                    POINTER(c_int64), c_int32]),

@@ -3,7 +3,9 @@ fixed number of iterations, Algorithm 1): 481x321 (K 400, T = 10), 1920x1080
 (K 2000, T = 20), the uneven batch of 64 images (T = 15) and the 4K batch
 (32 x 3840x2160, K 10000, T = 10).  Each workload is autotuned (kind, rows per
 chunk and waves per cell of the statistics pass, lanes per superpixel of the
-gather), then timed eagerly and with graph replay (the faster counts):
+gather, per-pass or persistent launches), then timed in three launch forms --
+per-pass launches, graph replay of the T passes, and one persistent
+cooperative launch of the T passes (the fastest counts):
 
   * Mpix/s per iteration = total pixels x iterations / wall time of the
     iterations (E-step, statistics, gather, LL and stop rule; inputs resident);
@@ -79,16 +81,18 @@ def end_to_end(dev, repeats: int):
 
 def measure(c: int, dev, repeats: int = 5) -> dict:
     """Per-iteration rates of workload c: autotuned schedule, wall time of T
-    iterations eager and with graph replay (median of `repeats`), and the
-    E-step alone from HIP events in one more eager run."""
+    iterations with per-pass launches, graph replay and the persistent launch
+    (median of `repeats`), and the E-step alone from HIP events in one more
+    run of per-pass launches."""
     name, ims, T = workload(c, dev)
     lab = synth.pack_batch(ims).contiguous()
     m = GMMSP([(im.W, im.H) for im in ims], K=[im.K for im in ims], device=dev)
     m.autotune(lab, passes=3, cache=None)
     sched = m.schedule()
 
-    def wall(graph: int) -> float:
+    def wall(graph: int, persistent: bool = False) -> float:
         m.set_graph_passes(graph)
+        m.set_persistent(persistent)
         m.init_seeds(lab)
         m.em_iterate(lab, T)                        # warm-up (graph capture)
         walls = []
@@ -102,7 +106,17 @@ def measure(c: int, dev, repeats: int = 5) -> dict:
         return float(np.median(walls))
 
     t_eager, t_graph = wall(0), wall(T)
-    t = min(t_eager, t_graph)
+    # the persistent launch runs the slot-lane pass (kind 1): timed with it
+    has_slots = m.cov_mode == 0 and m.get_slot_rows() > 0
+    t_pers = float("inf")
+    if has_slots:
+        m.set_estep_kernel(1)
+        t_pers = wall(0, True)
+        m.set_estep_kernel(sched["estep_kernel"])
+    forms = {"per_pass": t_eager, "graph": t_graph, "persistent": t_pers}
+    best_form = min(forms, key=forms.get)
+    t = forms[best_form]
+    m.set_persistent(bool(sched["persistent"]))
     # the E-step alone: an eager run with events around each launch (the
     # library replays no graph while it profiles)
     m.set_graph_passes(0)
@@ -121,6 +135,8 @@ def measure(c: int, dev, repeats: int = 5) -> dict:
              ms_per_iteration=round(1e3 * t / T, 4),
              ms_per_iteration_eager=round(1e3 * t_eager / T, 4),
              ms_per_iteration_graph=round(1e3 * t_graph / T, 4),
+             ms_per_iteration_persistent=(round(1e3 * t_pers / T, 4) if has_slots else None),
+             fastest_form=best_form, launch_form_ms=m.tune_persistent_ms,
              estep_ms_per_launch=round(est, 4),
              estep_gpx_per_s=round(p["pixel_evals"] / (p["estep_ms"] / 1e3) / 1e9, 2),
              pairs_per_pixel=round(p["pair_evals"] / p["pixel_evals"], 3),
@@ -145,18 +161,20 @@ def main():
         rows.append(r)
     if 1 in [int(x) for x in args.configs.split(",")]:
         end_to_end(dev, args.repeats)
-    print("| workload | Mpix/s per iteration | ms per iteration (eager / graph) | E-step us | "
-          "E-step Gpx/s | TFLOP/s | of 157.3 | schedule (kind, rows, waves per cell, "
-          "gather lanes) |")
+    print("| workload | Mpix/s per iteration | ms per iteration (per-pass / graph / persistent) | "
+          "E-step us | E-step Gpx/s | TFLOP/s | of 157.3 | schedule (kind, rows, waves per cell, "
+          "gather lanes, persistent) |")
     print("|---|---:|---|---:|---:|---:|---:|---|")
     for r in rows:
         sc = r["schedule"]
+        pers = r["ms_per_iteration_persistent"]
         print(f"| {r['workload']} | {r['mpix_per_s_per_iteration']:.0f} | "
-              f"{r['ms_per_iteration_eager']:.4f} / {r['ms_per_iteration_graph']:.4f} | "
+              f"{r['ms_per_iteration_eager']:.4f} / {r['ms_per_iteration_graph']:.4f} / "
+              f"{'-' if pers is None else f'{pers:.4f}'} | "
               f"{1e3 * r['estep_ms_per_launch']:.0f} | {r['estep_gpx_per_s']:.1f} | "
               f"{r['estep_tflops']:.1f} | {r['frac_of_157_3']:.2f} | "
               f"{sc['estep_kernel']}, {sc['rows_per_chunk']}, {sc['waves_per_cell']}, "
-              f"{sc['gather_lanes']} |")
+              f"{sc['gather_lanes']}, {sc['persistent']} |")
 
 
 if __name__ == "__main__":

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <string>
@@ -81,7 +82,7 @@ int check_params(const gmmsp_params* p) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t img, state, ll_hist, cell, sp, theta, rec, part, llp, n_done, total;
+  size_t img, state, ll_hist, cell, sp, theta, rec, part, llp, n_done, pers, total;
   int32_t n_cell = 0, n_sp = 0;
   int64_t n_pix = 0;
   int32_t cov_mode = 0;
@@ -135,6 +136,7 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
   L->part = o;    o = align256(o + sizeof(double) * kPartStride * kMaxWpc * n_cell);
   L->llp = o;     o = align256(o + sizeof(double) * kMaxWpc * n_cell);
   L->n_done = o;  o = align256(o + sizeof(int32_t));
+  L->pers = o;    o = align256(o + sizeof(PersistArea));
   L->total = o;
   L->n_cell = (int32_t)n_cell;
   L->n_sp = (int32_t)n_sp;
@@ -206,6 +208,12 @@ struct gmmsp_handle {
   const float* g_lab = nullptr;
   double g_tol = 0.0;
   int32_t g_len = 0, g_wpc = 0, g_glanes = 0, g_estep = -1, g_rc = 0;
+  // an upper bound of every image's pass count since the state's last reset
+  int64_t t_bound = 0;
+  // persistent T-mode passes: the workspace region and its pinned host image
+  bool persistent = false;
+  PersistArea* pers_dev = nullptr;
+  PersistArea* pers_host = nullptr;
   // E-step kernel timing
   bool profile = false;
   std::vector<hipEvent_t> ev;
@@ -217,6 +225,7 @@ struct gmmsp_handle {
     for (hipEvent_t e : done_ev)
       if (e) (void)hipEventDestroy(e);
     if (done_ring) (void)hipHostFree(done_ring);
+    if (pers_host) (void)hipHostFree(pers_host);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (gev_in) (void)hipEventDestroy(gev_in);
@@ -301,6 +310,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   P.part = (double*)(base + L.part);
   P.llp = (double*)(base + L.llp);
   P.n_done = (int32_t*)(base + L.n_done);
+  h->pers_dev = (PersistArea*)(base + L.pers);
   P.n_img = n_images;
   P.n_cell = L.n_cell;
   P.n_sp = L.n_sp;
@@ -328,6 +338,7 @@ int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_d
   if (e == hipSuccess) e = launch_reset_state(P, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->done_ring, sizeof(int32_t) * gmmsp_handle::kRing);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->pers_host, sizeof(PersistArea));
   for (int i = 0; i < gmmsp_handle::kRing && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&h->done_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -364,6 +375,7 @@ int gmmsp_init_seeds(gmmsp_handle* h, const float* lab_dev, void* stream) {
   if (!h || !lab_dev) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_init_seeds");
   h->initialised = true;
@@ -374,6 +386,7 @@ int gmmsp_set_params_dev(gmmsp_handle* h, const double* theta_dev, void* stream)
   if (!h || !theta_dev) return fail(GMMSP_E_INVAL, "null pointer");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_set_params(h->P, theta_dev, s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_set_params_dev");
   h->initialised = true;
@@ -389,6 +402,7 @@ int gmmsp_set_params(gmmsp_handle* h, const double* theta_host, void* stream) {
     return fail(GMMSP_E_SIZE, "staging area too small");
   hipError_t e = hipMemcpyAsync(h->P.part, theta_host, bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_set_params(h->P, h->P.part, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_set_params");
@@ -413,7 +427,7 @@ namespace {
 // rule, then the M-step gather.  Without the stop rule (rel_tol 0) no step of
 // the pass waits for L, and the gather's launch forms it too: two launches.
 // a and b (nullable) bracket the statistics pass with events.
-hipError_t em_pass(const DevPtrs& P, const float* lab, double rel_tol, hipStream_t s, hipEvent_t a,
+static hipError_t em_pass(const DevPtrs& P, const float* lab, double rel_tol, hipStream_t s, hipEvent_t a,
                    hipEvent_t b) {
   hipError_t e = hipSuccess;
   if (a) e = hipEventRecord(a, s);
@@ -429,7 +443,7 @@ hipError_t em_pass(const DevPtrs& P, const float* lab, double rel_tol, hipStream
 }
 
 // Capture `len` em passes into a graph on the handle's private stream.
-int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t len) {
+static int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t len) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   h->gexec = nullptr;
@@ -458,7 +472,7 @@ int capture_passes(gmmsp_handle* h, const float* lab, double rel_tol, int32_t le
 
 // Run whole chunks of graph_passes passes as graph launches; the stop test of
 // each chunk is read while the next chunk is already queued.
-int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, double rel_tol,
+static int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, double rel_tol,
                      hipStream_t s, int32_t* done_iters, bool* all_done) {
   hipError_t e = hipSuccess;
   if (!h->gstream) e = hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking);
@@ -501,6 +515,40 @@ int run_graph_chunks(gmmsp_handle* h, const float* lab, int32_t max_iters, doubl
   return GMMSP_OK;
 }
 
+// `iters` passes without the stop rule in one persistent launch (queued on s
+// after the copy of the barrier and the DevPtrs it runs with).
+static hipError_t persist_launch(gmmsp_handle* h, const float* lab, int32_t iters, hipStream_t s,
+                          hipEvent_t a = nullptr, hipEvent_t b = nullptr) {
+  h->pers_host->bar = GridBar{0u, 0u, 0, 0};
+  h->pers_host->P = h->P;
+  hipError_t e = hipMemcpyAsync(h->pers_dev, h->pers_host, sizeof(PersistArea),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && a) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = launch_persist(h->P, &h->pers_dev->P, lab, iters, &h->pers_dev->bar, s);
+  if (e == hipSuccess && b) e = hipEventRecord(b, s);
+  return e;
+}
+
+// Waits for the persistent launch and reports a grid barrier that ran out.
+static int persist_check(gmmsp_handle* h, hipError_t e, hipStream_t s, const char* what) {
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&h->pers_host->bar, &h->pers_dev->bar, sizeof(GridBar),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, what);
+  if (h->pers_host->bar.err)
+    return fail(GMMSP_E_STATE, "%s: a grid barrier wait ran out; the passes are incomplete", what);
+  return GMMSP_OK;
+}
+
+static int run_persistent(gmmsp_handle* h, const float* lab, int32_t iters, hipStream_t s) {
+  return persist_check(h, persist_launch(h, lab, iters, s), s, "persistent launch");
+}
+
+static bool persistent_applies(const gmmsp_handle* h, double rel_tol) {
+  return h->persistent && rel_tol <= 0.0 && !h->profile && h->P.cov_mode == 0 && h->P.estep == 1;
+}
+
 }  // namespace
 
 int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, double rel_tol,
@@ -510,14 +558,21 @@ int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, d
   if (max_iters < 0) return fail(GMMSP_E_INVAL, "max_iters < 0");
   hipStream_t s = (hipStream_t)stream;
   std::vector<ImgState> st(h->n_img);
-  hipError_t e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img,
-                                hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate");
-  int32_t tmax = 0;
-  for (const ImgState& x : st) tmax = x.t > tmax ? x.t : tmax;
-  if ((int64_t)tmax + max_iters > kLLCap)
-    return fail(GMMSP_E_STATE, "more than %d passes since the last initialisation", kLLCap);
+  hipError_t e = hipSuccess;
+  // The passes counted since the state was last reset bound every image's
+  // pass count; the device state is read (a wait for the stream) only when
+  // that bound leaves the history cap in doubt, or to time the passes.
+  if (h->profile || h->t_bound + max_iters > kLLCap) {
+    e = hipMemcpyAsync(st.data(), h->P.state, sizeof(ImgState) * h->n_img, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gmmsp_em_iterate");
+    int32_t tmax = 0;
+    for (const ImgState& x : st) tmax = x.t > tmax ? x.t : tmax;
+    h->t_bound = tmax;
+    if ((int64_t)tmax + max_iters > kLLCap)
+      return fail(GMMSP_E_STATE, "more than %d passes since the last initialisation", kLLCap);
+  }
+  h->t_bound += max_iters;  // at most this many passes follow, whatever happens below
   if (h->profile && (int32_t)h->ev.size() < 2 * max_iters) {
     const size_t need = 2 * (size_t)max_iters;
     while (h->ev.size() < need) {
@@ -530,7 +585,11 @@ int gmmsp_em_iterate(gmmsp_handle* h, const float* lab_dev, int32_t max_iters, d
   int32_t launched = 0;
   int32_t it = 0;
   bool all_done = false;
-  if (h->graph_passes > 0 && max_iters >= h->graph_passes && !h->profile) {
+  if (max_iters > 0 && persistent_applies(h, rel_tol)) {
+    int rc = run_persistent(h, lab_dev, max_iters, s);
+    if (rc) return rc;
+    it = launched = max_iters;
+  } else if (h->graph_passes > 0 && max_iters >= h->graph_passes && !h->profile) {
     int rc = run_graph_chunks(h, lab_dev, max_iters, rel_tol, s, &it, &all_done);
     if (rc) return rc;
     launched = it;
@@ -703,6 +762,21 @@ int gmmsp_get_gather_lanes(const gmmsp_handle* h, int32_t* lanes_per_superpixel)
   return GMMSP_OK;
 }
 
+int gmmsp_set_persistent(gmmsp_handle* h, int32_t on) {
+  if (!h) return fail(GMMSP_E_INVAL, "null handle");
+  if (on != 0 && on != 1) return fail(GMMSP_E_INVAL, "persistent flag %d not 0 or 1", on);
+  if (on && (h->P.cov_mode != 0 || !h->P.slot_j))
+    return fail(GMMSP_E_INVAL, "the persistent launch runs the slot-lane pass, which this batch has not");
+  h->persistent = on != 0;
+  return GMMSP_OK;
+}
+
+int gmmsp_get_persistent(const gmmsp_handle* h, int32_t* on) {
+  if (!h || !on) return fail(GMMSP_E_INVAL, "null pointer");
+  *on = h->persistent ? 1 : 0;
+  return GMMSP_OK;
+}
+
 int gmmsp_set_graph_passes(gmmsp_handle* h, int32_t passes) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (passes < 0 || passes > 256) return fail(GMMSP_E_INVAL, "graph passes %d outside [0, 256]", passes);
@@ -721,6 +795,7 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
+  h->t_bound = kLLCap;  // the tuner's passes are not counted: unknown until its last reset
   // candidates in order of preference: the slot-lane pass with each rows-per-
   // chunk value (largest first), then the pixel-lane pass; 1, 2, 4 waves per
   // cell each.  Index 3 v + w, v = 0..2 the rows values, v = 3 the pixel-lane
@@ -788,6 +863,7 @@ int gmmsp_autotune(gmmsp_handle* h, const float* lab_dev, int32_t passes, double
   if (h->P.slot_j) h->P.slot_rc = pick.rc;
   h->P.wpc = pick.wpc;
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune");
@@ -801,6 +877,7 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
   if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
   if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
   hipStream_t s = (hipStream_t)stream;
+  h->t_bound = kLLCap;  // the tuner's passes are not counted: unknown until its last reset
   const int32_t cand[3] = {1, 4, 16};
   const int n_cand = h->P.cov_mode != 0 ? 1 : 3;
   if (ms_host)
@@ -841,11 +918,84 @@ int gmmsp_autotune_gather(gmmsp_handle* h, const float* lab_dev, int32_t passes,
   if (b) (void)hipEventDestroy(b);
   h->P.glanes = pick;
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune_gather");
   h->initialised = true;
   *chosen = pick;
+  return GMMSP_OK;
+}
+
+int gmmsp_autotune_persistent(gmmsp_handle* h, const float* lab_dev, int32_t passes,
+                              double* ms_host, int32_t* chosen, void* stream) {
+  if (!h || !lab_dev || !chosen) return fail(GMMSP_E_INVAL, "null pointer");
+  if (passes < 1 || passes > 64) return fail(GMMSP_E_INVAL, "passes %d outside [1, 64]", passes);
+  hipStream_t s = (hipStream_t)stream;
+  h->t_bound = kLLCap;  // the tuner's passes are not counted: unknown until its last reset
+  if (ms_host)
+    for (int c = 0; c < 4; ++c) ms_host[c] = -1.0;
+  int rows[3] = {0, 0, 0};
+  const int n_rows =
+      h->P.cov_mode == 0 && h->P.slot_j ? slots_rows(h->P.slot_j, h->P.slot_rc_max, rows, 3) : 0;
+  const int32_t kind0 = h->P.estep, rc0 = h->P.slot_rc;
+  h->persistent = false;
+  hipError_t e = hipSuccess;
+  // candidate 0: per-pass launches with the schedule in effect; 1 + v: the
+  // persistent launch of the slot-lane pass with the v-th rows value.  Wall
+  // time from the first launch to the end of the last pass (host launch cost
+  // included: that is what the launch form changes), two rounds, each
+  // candidate's faster round counts.
+  double tmin[4] = {0.0, 0.0, 0.0, 0.0};
+  int rc = GMMSP_OK;
+  for (int round = 0; round < 2 && e == hipSuccess && rc == GMMSP_OK; ++round) {
+    for (int c = 0; c <= n_rows && e == hipSuccess && rc == GMMSP_OK; ++c) {
+      h->P.estep = c == 0 ? kind0 : 1;
+      if (h->P.slot_j) h->P.slot_rc = c == 0 ? rc0 : rows[c - 1];
+      e = launch_reset_state(h->P, s);
+      if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+      double ms = 0.0;
+      if (c == 0) {
+        for (int32_t i = 0; i < kTuneWarm && e == hipSuccess; ++i)
+          e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int32_t i = 0; i < passes && e == hipSuccess; ++i)
+          e = em_pass(h->P, lab_dev, 0.0, s, nullptr, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      } else {
+        rc = persist_check(h, persist_launch(h, lab_dev, kTuneWarm, s), s, "gmmsp_autotune_persistent");
+        const auto t0 = std::chrono::steady_clock::now();
+        if (rc == GMMSP_OK)
+          rc = persist_check(h, persist_launch(h, lab_dev, passes, s), s, "gmmsp_autotune_persistent");
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      if (round == 0 || ms < tmin[c]) tmin[c] = ms;
+    }
+  }
+  int pick = 0;
+  double best = tmin[0];
+  for (int c = 1; c <= n_rows; ++c)
+    if (tmin[c] < kTuneMargin * best && (pick == 0 || tmin[c] < tmin[pick])) pick = c;
+  if (ms_host)
+    for (int c = 0; c <= n_rows; ++c) ms_host[c] = tmin[c];
+  h->P.estep = pick == 0 ? kind0 : 1;
+  if (h->P.slot_j) h->P.slot_rc = pick == 0 ? rc0 : rows[pick - 1];
+  h->persistent = pick != 0;
+  if (rc != GMMSP_OK) {
+    h->P.estep = kind0;
+    h->P.slot_rc = rc0;
+    h->persistent = false;
+    return rc;
+  }
+  if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
+  if (e == hipSuccess) e = launch_init_seeds(h->P, lab_dev, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "gmmsp_autotune_persistent");
+  h->initialised = true;
+  *chosen = h->persistent ? 1 : 0;
   return GMMSP_OK;
 }
 
@@ -888,7 +1038,7 @@ struct WsLayoutSizes {
   size_t nbr, feat, x0, y, out, tgt, g4, g, wf[4], wt[4], part, grad, loss_part, loss_sum, total;
 };
 
-WsLayoutSizes ws_sizes(const gmmsp_handle* h) {
+static WsLayoutSizes ws_sizes(const gmmsp_handle* h) {
   WsLayoutSizes z{};
   const size_t n = (size_t)h->P.n_sp;
   z.nbr = n * 9 * sizeof(int32_t);
@@ -917,20 +1067,20 @@ WsLayoutSizes ws_sizes(const gmmsp_handle* h) {
   return z;
 }
 
-int ws_check(gmmsp_handle* h) {
+static int ws_check(gmmsp_handle* h) {
   if (!h) return fail(GMMSP_E_INVAL, "null handle");
   if (!h->ws.attached) return fail(GMMSP_E_STATE, "warm-start workspace not attached");
   return GMMSP_OK;
 }
 
-int ws_range(gmmsp_handle* h, int32_t b0, int32_t b1, int* p0, int* p1) {
+static int ws_range(gmmsp_handle* h, int32_t b0, int32_t b1, int* p0, int* p1) {
   if (b0 < 0 || b1 > h->n_img || b0 >= b1) return fail(GMMSP_E_INVAL, "image range [%d, %d)", b0, b1);
   *p0 = h->img[b0].sp_off;
   *p1 = b1 < h->n_img ? h->img[b1].sp_off : h->P.n_sp;
   return GMMSP_OK;
 }
 
-hipError_t ws_prep_all(gmmsp_handle* h, const float* params, hipStream_t s) {
+static hipError_t ws_prep_all(gmmsp_handle* h, const float* params, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (int l = 0; l < 4 && e == hipSuccess; ++l) {
     const WsLayer& L = kWs[l];
@@ -941,7 +1091,7 @@ hipError_t ws_prep_all(gmmsp_handle* h, const float* params, hipStream_t s) {
   return e;
 }
 
-hipError_t ws_forward_range(gmmsp_handle* h, const float* params, int p0, int p1, hipStream_t s) {
+static hipError_t ws_forward_range(gmmsp_handle* h, const float* params, int p0, int p1, hipStream_t s) {
   WsState& W = h->ws;
   hipError_t e = ws_prep_all(h, params, s);
   const uint16_t* in = W.x0;
@@ -1037,6 +1187,7 @@ int gmmsp_ws_apply(gmmsp_handle* h, const float* lab_dev, uint32_t output_mask, 
   double* rows = h->P.part;
   hipError_t e = ws_launch_apply(h->P, lab_dev, h->ws.out, output_mask, rows, s);
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e == hipSuccess) e = launch_set_params(h->P, rows, s);
   if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_apply");
   h->initialised = true;
@@ -1059,6 +1210,7 @@ int gmmsp_ws_apply_guarded(gmmsp_handle* h, const float* lab_dev, uint32_t outpu
   if (e == hipSuccess) e = launch_ll_eval(h->P, lab_dev, 0, s);
   if (e == hipSuccess) e = launch_seed_fallback(h->P, lab_dev, s);
   if (e == hipSuccess) e = launch_reset_state(h->P, s);
+  if (e == hipSuccess) h->t_bound = 0;
   if (e != hipSuccess) return hip_fail(e, "gmmsp_ws_apply_guarded");
   h->initialised = true;
   if (fallback_host) {
@@ -1161,7 +1313,7 @@ struct ConnSizes {
   int max_pix, max_tiles, max_w, max_h;
 };
 
-ConnSizes conn_sizes(const gmmsp_handle* h) {
+static ConnSizes conn_sizes(const gmmsp_handle* h) {
   ConnSizes z;
   z.max_pix = z.max_tiles = z.max_w = z.max_h = 0;
   for (const ImgDesc& I : h->img) {
@@ -1192,7 +1344,7 @@ int gmmsp_conn_workspace_bytes(const gmmsp_handle* h, size_t* bytes) {
 namespace {
 
 // The connectivity step on a given workspace; allocates nothing.
-int connectivity_run(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
+static int connectivity_run(gmmsp_handle* h, const float* lab_dev, const int32_t* labels_dev,
                      int32_t* out_dev, void* ws_dev, size_t ws_bytes, int32_t compact,
                      int32_t* counts_host, hipStream_t s) {
   if (h->n_pix >= ((int64_t)1 << 31) - 1)
@@ -1300,7 +1452,7 @@ struct MetricSizes {
   std::vector<int64_t> tab_off;
 };
 
-int metric_sizes(const gmmsp_handle* h, const int32_t* n_sp, const int32_t* n_gt, MetricSizes* z) {
+static int metric_sizes(const gmmsp_handle* h, const int32_t* n_sp, const int32_t* n_gt, MetricSizes* z) {
   z->tab_n = 0;
   z->n_rows = 0;
   int max_w = 0, max_h = 0;

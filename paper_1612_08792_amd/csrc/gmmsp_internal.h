@@ -152,6 +152,23 @@ __device__ inline void ll_commit(const DevPtrs& P, int b, double L, int mode, do
   st->t = t + 1;
 }
 
+// Grid barrier state of the persistent launch (device memory, zeroed before
+// each launch): arrivals at the current barrier, barriers completed, and an
+// error flag that a wait beyond its bound sets.
+struct GridBar {
+  uint32_t count;
+  uint32_t gen;
+  int32_t err;
+  int32_t pad;
+};
+
+// The persistent launch's region of the workspace: its barrier and the device
+// copy of the DevPtrs it runs with.
+struct PersistArea {
+  GridBar bar;
+  DevPtrs P;
+};
+
 // Launch wrappers (gmmsp_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_clear_records(const DevPtrs& P, hipStream_t s);
 hipError_t launch_init_seeds(const DevPtrs& P, const float* lab, hipStream_t s);
@@ -186,6 +203,11 @@ hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s)
 // the slot-lane pass's log-likelihood terms alone (no statistics), one wave per
 // cell: per-cell L terms in llp set 0
 hipError_t launch_ll_slots(const DevPtrs& P, const float* lab, hipStream_t s);
+// `iters` em passes without the stop rule in one cooperative launch of the
+// slot-lane pass (P.estep 1, P.cov_mode 0) and the gather; Pd a device copy
+// of P, gb zeroed, both written before the launch on stream s
+hipError_t launch_persist(const DevPtrs& P, const DevPtrs* Pd, const float* lab, int iters,
+                          GridBar* gb, hipStream_t s);
 
 // The 3x3 colour block (gmmsp_cov3.hip); mode: 0 statistics, 1 labels,
 // 2 responsibilities, 3 candidates.

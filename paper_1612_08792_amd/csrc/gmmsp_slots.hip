@@ -22,6 +22,7 @@
 // whitened colour coordinates (w, u1, u2), which the density computes anyway,
 // and are mapped back to Lab by the FP64 gather.  At the end of the cell the
 // seven lanes of each slot are added in a fixed order through LDS.
+#include "gmmsp_gather.h"
 #include "gmmsp_internal.h"
 #include "gmmsp_wave.h"
 
@@ -78,26 +79,23 @@ __device__ __forceinline__ float vreg(float x) {
 
 }  // namespace
 
-// STATS false: only the log-likelihood terms (phase 3, the partials and the
-// shifted e of the fallback are skipped), for evaluating L(theta) alone.
-template <int J, int RC, int WPC, bool STATS = true>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
-    DevPtrs P, const float* __restrict__ lab) {
+// One wave's share of one cell: wave `sub` of the cell's `wpc` waves (WPC, or
+// the run-time P.wpc when WPC is 0) takes chunks sub, sub + wpc, ...  PIX is
+// the wave's LDS (SlotLds<J, RC>::kWave floats).  STATS false: only the
+// log-likelihood terms (phase 3, the partials and the shifted e of the
+// fallback are skipped), for evaluating L(theta) alone.
+template <int J, int RC, int WPC, bool STATS>
+__device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restrict__ lab,
+                                          float* PIX, int cell, int sub) {
   // products are rounded where written: every shape of the kernel rounds alike
 #pragma clang fp contract(off)
   using LL = SlotLds<J, RC>;
-  __shared__ __align__(16) float lds[kWavesPerBlock * LL::kWave];
+  const int wpc = WPC > 0 ? WPC : P.wpc;
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  float* PIX = lds + wv * LL::kWave;
   float* E = PIX + LL::kPix;
   float* INV = E + LL::kE;
   float* SH = INV + LL::kInv;
   float* RED = E;
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + wv));
-  const int cell = __builtin_amdgcn_readfirstlane(gw / WPC);
-  const int sub = __builtin_amdgcn_readfirstlane(gw - cell * WPC);
-  if (cell >= P.n_cell) return;
   const AS4 CellDesc* cdp = cptr(P.cell) + cell;
   const int b = cdp->img, ccx = cdp->cx, ccy = cdp->cy;
   if (cptr(P.state)[b].done) return;
@@ -153,7 +151,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     pf1 = src[1];
     pf2 = src[2];
   }
-  for (int ch = sub; ch < n_chunks; ch += WPC) {
+  for (int ch = sub; ch < n_chunks; ch += wpc) {
     const int r0 = ch * RC;
     const int nr = min(RC, h - r0);
     // phase 0: stage this chunk's pixels, then fetch the next chunk's
@@ -165,7 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     wave_sync();
     {
-      const int cn = ch + WPC;
+      const int cn = ch + wpc;
       if (cn < n_chunks && p_r < min(RC, h - cn * RC)) {
         const float* src = img + 3 * ((cn * RC + p_r) * W + p_c);
         pf0 = src[0];
@@ -355,6 +353,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (lane == 0) P.llp[(size_t)sub * P.n_cell + cell] = kLn2 * (ll * 0x1p-22) + cst;
 }
 
+// One wave per (cell, sub) pair: WPC waves per cell.
+template <int J, int RC, int WPC, bool STATS = true>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
+    DevPtrs P, const float* __restrict__ lab) {
+  using LL = SlotLds<J, RC>;
+  __shared__ __align__(16) float lds[kWavesPerBlock * LL::kWave];
+  const int wv = threadIdx.x >> 6;
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + wv));
+  const int cell = __builtin_amdgcn_readfirstlane(gw / WPC);
+  const int sub = __builtin_amdgcn_readfirstlane(gw - cell * WPC);
+  if (cell >= P.n_cell) return;
+  slot_cell<J, RC, WPC, STATS>(P, lab, lds + wv * LL::kWave, cell, sub);
+}
+
 // Columns per lane and rows per chunk for cells up to max_w wide: J = ceil(max_w / 7),
 // RC x max_w <= 64 (one lane per pixel in phases 0 and 2).  0 when the slot-lane
 // kernel does not cover this width.
@@ -430,6 +442,151 @@ hipError_t launch_estep_slots(const DevPtrs& P, const float* lab, hipStream_t s)
   const int J = P.slot_j, RC = P.slot_rc;
 #define GMMSP_JRC(j, rc) \
   if (J == j && RC == rc) return launch_jrc<j, rc>(P, lab, s);
+  GMMSP_JRC(1, 8) GMMSP_JRC(1, 4) GMMSP_JRC(1, 2)
+  GMMSP_JRC(2, 4) GMMSP_JRC(2, 2) GMMSP_JRC(2, 1)
+  GMMSP_JRC(3, 3) GMMSP_JRC(3, 2) GMMSP_JRC(3, 1)
+  GMMSP_JRC(4, 2) GMMSP_JRC(4, 1)
+  GMMSP_JRC(5, 2) GMMSP_JRC(5, 1)
+  GMMSP_JRC(6, 1) GMMSP_JRC(7, 1) GMMSP_JRC(8, 1)
+#undef GMMSP_JRC
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent T-mode passes (Algorithm 1 without the stop rule): one
+// cooperative launch runs `iters` em passes.  Each pass is the statistics
+// pass over every (cell, sub) pair, a grid barrier, the gather of every
+// superpixel and L(theta^t) of every image (the work of the gather launch's
+// blocks, taken block by block), and a grid barrier.  Every work item runs the
+// per-pass kernels' code, so the passes are bitwise those of the eager
+// launches with the same schedule.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr long kBarrierSpins = 1l << 25;  // sleeps of about 50 ns: about 2 s
+
+// Grid-wide barrier of a cooperative launch (every block resident).  Every
+// wave first waits until its stores have reached the L2 (the vector memory
+// counter counts stores on this GPU); thread 0 of each block then arrives
+// with a device-scope acquire-release atomic add (its release writes the
+// XCD's L2 back, so the whole block's writes reach the device), waits with
+// relaxed loads and takes one device-scope acquire fence, whose invalidation
+// of the CU's L1 and the XCD's L2 serves the block's other waves too (they
+// share them), which __syncthreads orders after it.  A wait beyond
+// kBarrierSpins, or one that finds the error flag set, sets the flag and
+// returns false; the caller then leaves the kernel, so every block ends.
+__device__ bool grid_sync(GridBar* gb, uint32_t& gen) {
+  __shared__ int ok_s;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t g = gen;
+    int ok = 1;
+    if (__hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+        gridDim.x - 1) {
+      __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gb->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // relaxed polls: an acquire per poll would invalidate the XCD's L2 under
+      // the blocks still working; one acquire fence follows the wait
+      for (long n = 0;
+           __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g; ++n) {
+        if (n >= kBarrierSpins ||
+            __hip_atomic_load(&gb->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          __hip_atomic_store(&gb->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    gen = g + 1u;
+    ok_s = ok;
+    __builtin_amdgcn_s_waitcnt(0);  // the acquire's cache invalidation has completed
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// The gather phase's block blk (a call, so that its FP64 registers do not
+// crowd the statistics pass's)
+__device__ __noinline__ void persist_gather(const DevPtrs& P, int blk, int n_fin) {
+  if (blk < n_fin)
+    finalize_block(P, blk);
+  else
+    ll_reduce_block(P, blk - n_fin, 0.0, LL_EM, P.wpc);
+}
+
+}  // namespace
+
+// Pd: a device copy of the pass's DevPtrs (read-only here), so that the
+// gather's call takes it by reference without a private copy
+template <int J, int RC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_persist(
+    const DevPtrs* __restrict__ Pd, const float* __restrict__ lab, int iters, int n_fin,
+    GridBar* gb) {
+  const DevPtrs& P = *Pd;
+  using LL = SlotLds<J, RC>;
+  __shared__ __align__(16) float lds[kWavesPerBlock * LL::kWave];
+  const int wv = threadIdx.x >> 6;
+  const int n_units = P.n_cell * P.wpc;
+  const int n_waves = (int)gridDim.x * kWavesPerBlock;
+  uint32_t gen = 0;
+  for (int t = 0; t < iters; ++t) {
+    for (int u = (int)blockIdx.x * kWavesPerBlock + wv; u < n_units; u += n_waves) {
+      const int gw = __builtin_amdgcn_readfirstlane(u);
+      const int cell = __builtin_amdgcn_readfirstlane(gw / P.wpc);
+      const int sub = __builtin_amdgcn_readfirstlane(gw - cell * P.wpc);
+      slot_cell<J, RC, 0, true>(P, lab, lds + wv * LL::kWave, cell, sub);
+    }
+    if (!grid_sync(gb, gen)) return;
+    for (int blk = blockIdx.x; blk < n_fin + P.n_img; blk += gridDim.x)
+      persist_gather(P, blk, n_fin);
+    if (!grid_sync(gb, gen)) return;
+  }
+}
+
+namespace {
+template <int J, int RC>
+hipError_t launch_persist_jrc(const DevPtrs& P, const DevPtrs* Pd, const float* lab, int iters,
+                              GridBar* gb, hipStream_t s) {
+  // resident blocks of this kernel per device, queried once (0: not yet)
+  constexpr int kMaxDev = 64;
+  static int resident[kMaxDev] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  if (resident[dev] == 0) {
+    int n_cu = 0, coop = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<J, RC>, 256, 0);
+    if (e != hipSuccess) return e;
+    if (!coop || per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+    resident[dev] = per_cu * n_cu;
+  }
+  const int per = 256 / P.glanes;  // superpixels per gather block
+  int n_fin = (int)((P.n_sp + per - 1) / per);
+  const long need_e = ((long)P.n_cell * P.wpc + kWavesPerBlock - 1) / kWavesPerBlock;
+  const long need = need_e > (long)n_fin + P.n_img ? need_e : (long)n_fin + P.n_img;
+  const long cap = resident[dev];
+  const unsigned grid = (unsigned)(need < cap ? need : cap);
+  const float* l = lab;
+  void* args[] = {&Pd, &l, &iters, &n_fin, &gb};
+  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_persist<J, RC>), dim3(grid),
+                                 dim3(256), args, 0, s);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_persist(const DevPtrs& P, const DevPtrs* Pd, const float* lab, int iters,
+                          GridBar* gb, hipStream_t s) {
+  const int J = P.slot_j, RC = P.slot_rc;
+#define GMMSP_JRC(j, rc) \
+  if (J == j && RC == rc) return launch_persist_jrc<j, rc>(P, Pd, lab, iters, gb, s);
   GMMSP_JRC(1, 8) GMMSP_JRC(1, 4) GMMSP_JRC(1, 2)
   GMMSP_JRC(2, 4) GMMSP_JRC(2, 2) GMMSP_JRC(2, 1)
   GMMSP_JRC(3, 3) GMMSP_JRC(3, 2) GMMSP_JRC(3, 1)

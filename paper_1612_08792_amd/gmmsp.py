@@ -204,9 +204,11 @@ class GMMSP:
 
     def schedule(self) -> dict:
         """The schedule in effect: statistics-pass kind, rows per chunk, waves
-        per cell, gather lanes."""
+        per cell, gather lanes, and whether T-mode passes run as one
+        persistent launch."""
         return {"estep_kernel": self.get_estep_kernel(), "rows_per_chunk": self.get_slot_rows(),
-                "waves_per_cell": self.get_schedule(), "gather_lanes": self.get_gather_lanes()}
+                "waves_per_cell": self.get_schedule(), "gather_lanes": self.get_gather_lanes(),
+                "persistent": self.get_persistent()}
 
     def set_gather_lanes(self, lanes_per_superpixel: int):
         check(lib().gmmsp_set_gather_lanes(self.handle, int(lanes_per_superpixel)))
@@ -219,6 +221,16 @@ class GMMSP:
     def set_graph_passes(self, passes: int):
         check(lib().gmmsp_set_graph_passes(self.handle, int(passes)))
 
+    def set_persistent(self, on: bool):
+        """T-mode passes (no stop rule) of the slot-lane pass as one persistent
+        cooperative launch per em_iterate call."""
+        check(lib().gmmsp_set_persistent(self.handle, 1 if on else 0))
+
+    def get_persistent(self) -> int:
+        v = c_int32()
+        check(lib().gmmsp_get_persistent(self.handle, byref(v)))
+        return v.value
+
     def geometry_key(self) -> str:
         dev = torch.cuda.get_device_name(self.device)
         grids = ";".join(f"{W}x{H}/{g.vx}x{g.vy}" for (W, H), g in zip(self.sizes, self.grids))
@@ -228,8 +240,9 @@ class GMMSP:
 
     def autotune(self, lab: torch.Tensor, passes: int = 3, cache: str | None = "default") -> int:
         """Pick the statistics-pass schedule (kind, rows per chunk, waves per
-        cell), then the lanes per superpixel of the gather, by timing them on
-        this batch (native loops in the library); results are cached by batch
+        cell), then the lanes per superpixel of the gather, then per-pass or
+        persistent T-mode launches, by timing them on this batch (native
+        loops in the library); results are cached by batch
         geometry in a JSON file (~/.cache/gmmsp/schedules.json unless another
         path or None is given).  Returns the waves per cell.  Leaves the handle
         initialised by init_seeds."""
@@ -255,6 +268,7 @@ class GMMSP:
                 self.set_slot_rows(int(entry["rows_per_chunk"]))
             self.set_schedule(int(entry["waves_per_cell"]))
             self.set_gather_lanes(int(entry.get("lanes_per_superpixel", 1)))
+            self.set_persistent(bool(entry.get("persistent", 0)))
             self.init_seeds(lab)
             self.tune_cached = True
             return self.get_schedule()
@@ -272,11 +286,22 @@ class GMMSP:
                                           c_void_p(gms.ctypes.data), byref(lanes),
                                           c_void_p(self._stream())))
         self.tune_gather_ms = dict(zip((1, 4, 16), gms.tolist()))
+        pms = np.zeros(4)
+        pers = c_int32()
+        # the launch form's fixed cost is amortised over the T passes of a run:
+        # time at least the paper's T = 10
+        check(lib().gmmsp_autotune_persistent(self.handle, self._lab(lab), max(int(passes), 10),
+                                              c_void_p(pms.ctypes.data), byref(pers),
+                                              c_void_p(self._stream())))
+        # per-pass launches, then the persistent launch per rows value (largest first)
+        self.tune_persistent_ms = {k: float(v) for k, v in
+                                   zip(("per_pass", "r0", "r1", "r2"), pms) if v >= 0}
         if path:
             table[key] = {"estep_kernel": self.get_estep_kernel(),
                           "rows_per_chunk": self.get_slot_rows(),
                           "waves_per_cell": w.value, "ms": self.tune_ms,
-                          "lanes_per_superpixel": lanes.value, "gather_ms": self.tune_gather_ms}
+                          "lanes_per_superpixel": lanes.value, "gather_ms": self.tune_gather_ms,
+                          "persistent": pers.value, "persistent_ms": self.tune_persistent_ms}
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path, "w") as f:
                 json.dump(table, f, indent=1)

@@ -128,6 +128,9 @@ def test_create_rejects_bad_arguments_before_any_device_work():
     assert L.gmmsp_set_gather_lanes(None, 16) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_get_gather_lanes(None, byref(c_int32())) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_autotune_gather(None, None, 1, None, byref(c_int32()), None) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_set_persistent(None, 1) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_get_persistent(None, byref(c_int32())) == _lib.GMMSP_E_INVAL
+    assert L.gmmsp_autotune_persistent(None, None, 1, None, byref(c_int32()), None) == _lib.GMMSP_E_INVAL
 
 
 def test_connectivity_rejects_bad_arguments_before_any_device_work():
