@@ -353,14 +353,21 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
   if (lane == 0) P.llp[(size_t)sub * P.n_cell + cell] = kLn2 * (ll * 0x1p-22) + cst;
 }
 
-// One wave per (cell, sub) pair: WPC waves per cell.
+// One wave per (cell, sub) pair: WPC waves per cell.  The blocks of a launch
+// go to the eight XCDs in turn (block b to XCD b mod 8); block b takes the
+// cells of logical block lb, so that each XCD works through one contiguous run
+// of cells and the cache lines that neighbouring cells share (pixel rows that
+// cross a cell border) are fetched into one L2 rather than two.
 template <int J, int RC, int WPC, bool STATS = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_slots(
     DevPtrs P, const float* __restrict__ lab) {
   using LL = SlotLds<J, RC>;
   __shared__ __align__(16) float lds[kWavesPerBlock * LL::kWave];
   const int wv = threadIdx.x >> 6;
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + wv));
+  const int nb = (int)gridDim.x, x = (int)blockIdx.x % 8, i = (int)blockIdx.x / 8;
+  const int per = nb / 8, rem = nb % 8;
+  const int lb = x * per + (x < rem ? x : rem) + i;  // a bijection of [0, nb)
+  const int gw = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + wv);
   const int cell = __builtin_amdgcn_readfirstlane(gw / WPC);
   const int sub = __builtin_amdgcn_readfirstlane(gw - cell * WPC);
   if (cell >= P.n_cell) return;
