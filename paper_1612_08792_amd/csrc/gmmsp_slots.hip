@@ -63,11 +63,15 @@ struct SlotLds {
   static constexpr int kWave = kPix + kTail;
 };
 
-// LDS writes of this wave become visible to all of its lanes
+// LDS writes of this wave become visible to all of its lanes.  Wavefront
+// scope: a wave's LDS operations are carried out in the order it issues them,
+// so the fences only keep the compiler from moving LDS accesses across the
+// barrier, and no wait for the LDS is needed (a workgroup-scope fence would
+// wait for every outstanding LDS operation, four times per chunk).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // keep a wave-uniform value in a vector register, so that the instructions
