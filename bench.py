@@ -279,7 +279,7 @@ def main():
                          "reference kernel that scales rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(images would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
 
