@@ -103,6 +103,9 @@ typedef struct gmmsp_handle gmmsp_handle;
  * between two initialisations. */
 #define GMMSP_LL_CAP 4096
 
+/* Widest image a batch may hold (2^24 pixels). */
+#define GMMSP_MAX_WIDTH 16777216
+
 /* Host only.  Seed grid of one image by Eqs. vxy and nxyK.
  * Errors: E_INVAL (null pointer, W or H < 1, K outside [1, W H] when v is
  * derived, v_x or v_y < 1), E_SIZE (n_x or n_y would be 0). */
@@ -111,7 +114,8 @@ int gmmsp_grid(const gmmsp_params* params, gmmsp_grid_info* out);
 /* Host only.  Device workspace, in bytes, for a batch of n_images images with
  * parameters params[0..n_images-1].  Errors: those of gmmsp_grid, E_INVAL for
  * cov_mode outside 0..3, different cov_mode values in one batch, or a
- * non-positive eps_s, eps_c, lambda. */
+ * non-positive eps_s, eps_c, lambda; E_SIZE for an image wider than
+ * GMMSP_MAX_WIDTH pixels. */
 int gmmsp_workspace_bytes(int32_t n_images, const gmmsp_params* params, size_t* bytes);
 
 /* Create a handle over caller-owned device workspace (at least

@@ -100,6 +100,9 @@ int plan(int32_t n, const gmmsp_params* params, Layout* L, std::vector<ImgDesc>*
     if (rc) return fail(rc, "image %d: %s", b, g_err.c_str());
     if (params[b].cov_mode != params[0].cov_mode)
       return fail(GMMSP_E_INVAL, "image %d: every image of a batch needs the same cov_mode", b);
+    // the E-step addresses a chunk's rows by 32-bit byte offsets from its first row
+    if (params[b].W > kMaxWidth)
+      return fail(GMMSP_E_SIZE, "image %d: wider than %d pixels", b, kMaxWidth);
     if (descs) {
       ImgDesc& d = (*descs)[b];
       memset(&d, 0, sizeof(d));
@@ -164,6 +167,7 @@ constexpr WsLayer kWs[4] = {
 constexpr int kWsParams = 26026;
 constexpr int kWsMaxSplits = 1024;
 static_assert(kWsParams == GMMSP_WS_NPARAM, "parameter count");
+static_assert(kMaxWidth == GMMSP_MAX_WIDTH, "widest image");
 
 struct WsState {
   bool attached = false;

@@ -16,6 +16,7 @@ constexpr int kThetaRow = 13;      // doubles per superpixel in the FP64 master
 constexpr int kLLCap = 4096;       // log-likelihood history entries per image
 constexpr int kWavesPerBlock = 4;  // 64-lane waves per block of the per-cell kernels
 constexpr int kMaxWpc = 4;         // largest number of waves sharing one cell
+constexpr int kMaxWidth = 1 << 24; // widest image: a chunk's byte offsets fit 32 bits
 // the unified 3x3 colour block (cov_mode 1)
 constexpr int kRec3 = 20;          // floats per cell-slot record
 constexpr int kStats3 = 15;        // N, S1 (5), S2 (xx xy yy LL La Lb aa ab bb)

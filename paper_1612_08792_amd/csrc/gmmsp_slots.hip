@@ -81,6 +81,14 @@ __device__ __forceinline__ float vreg(float x) {
   return x;
 }
 
+// an LDS address that the compiler keeps in a register as an opaque value,
+// instead of recomputing it from the lane index in every chunk
+__device__ __forceinline__ float* lds_hold(float* p) {
+  auto q = (__attribute__((address_space(3))) float*)p;
+  asm volatile("" : "+v"(q));
+  return (float*)q;
+}
+
 }  // namespace
 
 // One wave's share of one cell: wave `sub` of the cell's `wpc` waves (WPC, or
@@ -147,14 +155,33 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
   double ll64 = 0.0;  // sum of the pixels' log2 terms, in units of 2^-22
 
   const int n_chunks = (h + RC - 1) / RC;
-  // prefetch of the first chunk's pixel
+  // the lane's staged pixel: byte offset from the first pixel of its chunk,
+  // below 12 RC W, a 32-bit offset from a wave-uniform row address
+  static_assert(12LL * RC * kMaxWidth < (1LL << 32), "32-bit pixel offsets");
+  const uint32_t p_ofs = 12u * ((uint32_t)p_r * (uint32_t)W + (uint32_t)p_c);
   float pf0 = 0.f, pf1 = 0.f, pf2 = 0.f;
-  if (sub < n_chunks && p_r < min(RC, h - sub * RC)) {
-    const float* src = img + 3 * ((sub * RC + p_r) * W + p_c);
-    pf0 = src[0];
-    pf1 = src[1];
-    pf2 = src[2];
-  }
+  auto fetch = [&](int c) {
+    if (c < n_chunks && p_r < min(RC, h - c * RC)) {
+      const char* row = reinterpret_cast<const char*>(img + (size_t)3 * W * (c * RC));
+      const float* src = reinterpret_cast<const float*>(row + p_ofs);
+      pf0 = src[0];
+      pf1 = src[1];
+      pf2 = src[2];
+    }
+  };
+  fetch(sub);  // prefetch of the first chunk's pixel
+  // loop-invariant LDS addresses of phases 2 and 3: the pixel's e in slots
+  // 0-2, 3-5 and 6-8, and the lane's column phase of 1/sum
+  constexpr int kSE = kQ * LL::kEB;  // e floats per slot
+  static_assert(kSlots == 9, "phase 2 adds nine slots");
+  const float* const e0 = lds_hold(E + p_e);
+  const float* const e3 = lds_hold(E + 3 * kSE + p_e);
+  const float* const e6 = lds_hold(E + 6 * kSE + p_e);
+  // (16-byte aligned: kEB and the offset of INV are multiples of 4 floats,
+  // and a row of kEB floats holds the RC J values rounded up to 4)
+  const float4* const ivs = reinterpret_cast<const float4*>(lds_hold(INV + q * LL::kEB));
+  static_assert(LL::kEB % 4 == 0 && (LL::kPix + LL::kE) % 4 == 0 &&
+                (RC * J + 3) / 4 * 4 <= LL::kEB, "16-byte reads of 1/sum");
   for (int ch = sub; ch < n_chunks; ch += wpc) {
     const int r0 = ch * RC;
     const int nr = min(RC, h - r0);
@@ -166,15 +193,7 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
       PIX[p_x + 2] = pf2;
     }
     wave_sync();
-    {
-      const int cn = ch + wpc;
-      if (cn < n_chunks && p_r < min(RC, h - cn * RC)) {
-        const float* src = img + 3 * ((cn * RC + p_r) * W + p_c);
-        pf0 = src[0];
-        pf1 = src[1];
-        pf2 = src[2];
-      }
-    }
+    fetch(ch + wpc);
     // phase 1: log densities (log2 units, Eq. gaussian) and e = 2^l
     float e[RC][J], tw[RC][J], tu1[RC][J], tu2[RC][J];
     float cr[RC], rrv[RC];
@@ -182,9 +201,7 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
     for (int i = 0; i < RC; ++i) {
       rrv[i] = vreg((float)(r0 + i));
       const float t2 = fmaf(L22, rrv[i], O2);
-      // a row past the cell's end gets -inf (a wave-uniform addend, no select)
-      const float rowoff = i < nr ? 0.f : -INFINITY;
-      cr[i] = fmaf(-t2, t2, C) + rowoff;
+      cr[i] = fmaf(-t2, t2, C);
       const float* px = PIX + q * LL::kPB + i * J * 3;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -217,44 +234,44 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
     wave_sync();
     // phase 2: the denominator of Eq. Rik for each pixel of the chunk
     const bool pv = p_r < nr;
+    // a lane without a pixel gets sum 1 (log-likelihood term 0)
     float sm = 1.f;
     if (pv) {
-      sm = E[p_e];
-#pragma unroll
-      for (int k = 1; k < kSlots; ++k) sm += E[k * kQ * LL::kEB + p_e];
+      sm = e0[0];
+      sm += e0[kSE];
+      sm += e0[2 * kSE];
+      sm += e3[0];
+      sm += e3[kSE];
+      sm += e3[2 * kSE];
+      sm += e6[0];
+      sm += e6[kSE];
+      sm += e6[2 * kSE];
     }
-    const bool small = pv && sm < 0x1p-100f;
-    float inv = 0.f, lg = 0.f;
-    if (__builtin_amdgcn_ballot_w64(small) == 0) {
-      inv = __builtin_amdgcn_rcpf(sm);
-      lg = __builtin_amdgcn_logf(sm);
-    } else {
+    const bool small = sm < 0x1p-100f;  // only a pixel's sum can be small
+    float inv = __builtin_amdgcn_rcpf(sm), lg = __builtin_amdgcn_logf(sm);
+    if (__builtin_amdgcn_ballot_w64(small) != 0) {
       // A pixel whose nine densities all underflow is normalised with its
       // largest log density subtracted first (the same posterior, Eq. Rik,
-      // without 0/0); every other pixel keeps its e.  The log densities
-      // replace e in LDS.
+      // without 0/0); every other pixel keeps its e, inv and lg.  The log
+      // densities replace e in LDS.
       float* dst = E + (s * kQ + q) * LL::kEB;
 #pragma unroll
       for (int i = 0; i < RC; ++i)
 #pragma unroll
         for (int j = 0; j < J; ++j) dst[i * J + j] = log_density(i, j);
       wave_sync();
-      if (pv) {
-        if (small) {
-          float m = E[p_e];
+      if (small) {
+        float m = E[p_e];
 #pragma unroll
-          for (int k = 1; k < kSlots; ++k) m = fmaxf(m, E[k * kQ * LL::kEB + p_e]);
-          float t = 0.f;
+        for (int k = 1; k < kSlots; ++k) m = fmaxf(m, E[k * kQ * LL::kEB + p_e]);
+        float t = 0.f;
 #pragma unroll
-          for (int k = 0; k < kSlots; ++k) t += __builtin_amdgcn_exp2f(E[k * kQ * LL::kEB + p_e] - m);
-          inv = __builtin_amdgcn_rcpf(t);
-          lg = __builtin_amdgcn_logf(t) + m;
-          SH[p_e] = m;
-        } else {
-          inv = __builtin_amdgcn_rcpf(sm);
-          lg = __builtin_amdgcn_logf(sm);
-          SH[p_e] = INFINITY;  // not shifted
-        }
+        for (int k = 0; k < kSlots; ++k) t += __builtin_amdgcn_exp2f(E[k * kQ * LL::kEB + p_e] - m);
+        inv = __builtin_amdgcn_rcpf(t);
+        lg = __builtin_amdgcn_logf(t) + m;
+        SH[p_e] = m;
+      } else if (p_r < RC) {
+        SH[p_e] = INFINITY;  // not shifted (also every position past the last row)
       }
       if constexpr (STATS) {
         wave_sync();
@@ -268,26 +285,36 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
           }
       }
     }
-    if (pv) {
-      if constexpr (STATS) INV[p_e] = inv;
-      // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
-      // integer-valued FP64 sums are exact, so L does not depend on how pixels
-      // are grouped into chunks and lanes.  lg * 2^22 is exact in FP32, so
-      // rounding it there equals rounding it in FP64.
-      ll64 += (double)rintf(lg * 0x1p22f);
+    // a position past the cell's last row gets 1/sum = 0, so its finite e
+    // (from a stale pixel) has R = 0 in phase 3
+    if constexpr (STATS) {
+      if (p_r < RC) INV[p_e] = pv ? inv : 0.f;
     }
+    // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
+    // integer-valued FP64 sums are exact, so L does not depend on how pixels
+    // are grouped into chunks and lanes.  lg * 2^22 is exact in FP32, so
+    // rounding it there equals rounding it in FP64.
+    ll64 += (double)rintf(lg * 0x1p22f);
     if constexpr (!STATS) continue;
     wave_sync();
     // phase 3: R = e / sum and the slot's sufficient statistics
     {
-      const float* ivs = INV + q * LL::kEB;
+      float iv[(RC * J + 3) / 4 * 4];
+#pragma unroll
+      for (int k = 0; k < (RC * J + 3) / 4; ++k) {
+        const float4 v = ivs[k];
+        iv[4 * k] = v.x;
+        iv[4 * k + 1] = v.y;
+        iv[4 * k + 2] = v.z;
+        iv[4 * k + 3] = v.w;
+      }
 #pragma unroll
       for (int i = 0; i < RC; ++i) {
         const float rr = rrv[i];
         const float r2 = vreg(rr * rr);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          const float R = e[i][j] * ivs[i * J + j];
+          const float R = e[i][j] * iv[i * J + j];
           Nj[j] += R;
           Mj[j] = fmaf(rr, R, Mj[j]);
           Qj[j] = fmaf(r2, R, Qj[j]);

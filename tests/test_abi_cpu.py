@@ -111,6 +111,11 @@ def test_workspace_bytes_and_validation():
     bad = (_lib.GmmspParams * 1)(make_params(481, 321, 400, eps_c=0.0))
     assert L.gmmsp_workspace_bytes(1, bad, byref(n)) == _lib.GMMSP_E_INVAL
     assert L.gmmsp_workspace_bytes(0, arr, byref(n)) == _lib.GMMSP_E_INVAL
+    # the widest image the E-step addresses with 32-bit offsets is 2^24 pixels
+    wide = (_lib.GmmspParams * 1)(make_params(1 << 24, 64, 1 << 20))
+    assert L.gmmsp_workspace_bytes(1, wide, byref(n)) == 0
+    wide = (_lib.GmmspParams * 1)(make_params((1 << 24) + 1, 64, 1 << 20))
+    assert L.gmmsp_workspace_bytes(1, wide, byref(n)) == _lib.GMMSP_E_SIZE
 
 
 def test_create_rejects_bad_arguments_before_any_device_work():
