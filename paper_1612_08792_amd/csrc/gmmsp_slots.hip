@@ -192,6 +192,13 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
       PIX[p_x + 1] = pf1;
       PIX[p_x + 2] = pf2;
     }
+    if constexpr (STATS) {
+      // a position past the cell's last row (in the cell's last chunk) gets
+      // 1/sum = 0, so its finite e (from a stale pixel) has R = 0 in phase 3
+      if (nr < RC) {
+        if (p_r >= nr && p_r < RC) INV[p_e] = 0.f;
+      }
+    }
     wave_sync();
     fetch(ch + wpc);
     // phase 1: log densities (log2 units, Eq. gaussian) and e = 2^l
@@ -260,6 +267,7 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
 #pragma unroll
         for (int j = 0; j < J; ++j) dst[i * J + j] = log_density(i, j);
       wave_sync();
+      if (p_r < RC) SH[p_e] = INFINITY;  // not shifted (also every position past the last row)
       if (small) {
         float m = E[p_e];
 #pragma unroll
@@ -270,8 +278,6 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
         inv = __builtin_amdgcn_rcpf(t);
         lg = __builtin_amdgcn_logf(t) + m;
         SH[p_e] = m;
-      } else if (p_r < RC) {
-        SH[p_e] = INFINITY;  // not shifted (also every position past the last row)
       }
       if constexpr (STATS) {
         wave_sync();
@@ -285,10 +291,8 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
           }
       }
     }
-    // a position past the cell's last row gets 1/sum = 0, so its finite e
-    // (from a stale pixel) has R = 0 in phase 3
     if constexpr (STATS) {
-      if (p_r < RC) INV[p_e] = pv ? inv : 0.f;
+      if (pv) INV[p_e] = inv;
     }
     // the log-likelihood term of the pixel (log2 units) on a 2^-22 grid: the
     // integer-valued FP64 sums are exact, so L does not depend on how pixels

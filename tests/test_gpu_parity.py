@@ -232,6 +232,36 @@ def test_far_outlier_pixel_uses_shifted_softmax(dev):
     assert out["ll_final"] == pytest.approx(ref["ll_final"], rel=1e-6)
 
 
+@pytest.mark.parametrize("rows", [1, 2, 3])
+def test_outliers_in_a_cells_last_chunk(dev, rows):
+    # 15 x 17 cells: with 2 or 3 rows per chunk a cell's last chunk is short, and
+    # its positions past the last row hold the previous chunk's values.  Outliers
+    # in rows 1, 2 and 16 of one column send earlier chunks and the last chunk
+    # through the shifted normalisation at the same positions.  One step from
+    # the oracle's theta^2.
+    W, H, v = 60, 51, (15, 17)
+    im = synth.voronoi_lab(W, H, 4, 2.0, 13, 12)
+    lab = im.lab.clone()
+    lab[1, 3] = torch.tensor([900.0, -800.0, 700.0])
+    lab[2, 3] = torch.tensor([-700.0, 900.0, -800.0])
+    lab[16, 3] = torch.tensor([800.0, 700.0, -900.0])
+    say(f"{W}x{H} v {v}, rows per chunk {rows}, outliers in rows 1, 2, 16")
+    g = O.make_grid(W, H, vx=v[0], vy=v[1])
+    res = O.run_em(lab.numpy(), g, max_iters=2)
+    m = GMMSP([(W, H)], v=v, device=dev)
+    m.set_estep_kernel(1)
+    m.set_slot_rows(rows)
+    d = lab.reshape(-1).to(dev)
+    m.set_params(O.theta_to_rows(res["theta"]))
+    R = m.export_responsibilities(d).cpu().numpy()
+    assert np.isfinite(R).all()
+    assert np.abs(R - oracle_slots(g, res["cand"], res["R"])).max() <= 1e-5
+    m.em_iterate(d, 1)
+    assert m.ll_history(0)[0] == pytest.approx(res["ll_final"], rel=1e-7)
+    th1 = O.mstep(res["z"], g, res["R"], res["pos"], res["theta"], O.Params())
+    assert_theta_close(m.get_params(), O.theta_to_rows(th1), 1e-5, what=f"rows {rows}")
+
+
 # ---------------------------------------------------------------------------
 # full-size 4K image: sampled one-step parity in the launch shape of the bench
 # ---------------------------------------------------------------------------
