@@ -103,8 +103,7 @@ __device__ inline void write_record_slot(const DevPtrs& P, const ImgDesc& I, int
   r[R_ML] = (float)q.mL;
   r[R_MA] = (float)q.ma;
   r[R_MB] = (float)q.mb;
-  float4* dst = reinterpret_cast<float4*>(
-      P.rec + ((size_t)(I.cell_off + cy * I.ncx + cx) * kSlots + slot) * kRecFloats);
+  float4* dst = reinterpret_cast<float4*>(P.rec + rec_index(P.n_cell, I.cell_off + cy * I.ncx + cx, slot));
 #pragma unroll
   for (int j = 0; j < kRecFloats / 4; ++j)
     dst[j] = make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
@@ -201,7 +200,7 @@ struct ColourFrame {
 };
 
 __device__ inline ColourFrame colour_frame(const DevPtrs& P, const ImgDesc& I, const SpDesc& d) {
-  const float* f = P.rec + ((size_t)(I.cell_off + d.ky * I.ncx + d.kx) * kSlots + 4) * kRecFloats;
+  const float* f = P.rec + rec_index(P.n_cell, I.cell_off + d.ky * I.ncx + d.kx, 4);
   return ColourFrame{f[R_SL], f[R_OL], f[R_A11], f[R_A12], f[R_A22], f[R_O3], f[R_O4]};
 }
 

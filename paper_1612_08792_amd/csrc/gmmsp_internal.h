@@ -45,6 +45,13 @@ inline int rec_floats_of(int cov_mode) {
   return cov_mode == 0 ? kRecFloats : cov_mode == 1 ? kRec3 : cov_mode == 2 ? kRecF : kRecG;
 }
 
+// First float of the split-colour-block record of candidate slot `slot` of batch
+// cell `cell`.  Slot-major: the gather's threads (consecutive superpixels of a
+// grid row) write the records of consecutive cells for each slot, whole lines.
+__host__ __device__ inline size_t rec_index(int n_cell, int cell, int slot) {
+  return ((size_t)slot * n_cell + cell) * kRecFloats;
+}
+
 // Cell-slot record: the parameters of the superpixel in slot s of cell c, in
 // float32 and folded with the cell's origin, so that for a pixel at (xr, yr)
 // relative to the cell origin with colour (L, a, b):
@@ -100,7 +107,8 @@ struct DevPtrs {
   const CellDesc* cell;
   const SpDesc* sp;
   double* theta;            // [n_sp][kThetaRow] FP64 master
-  float* rec;               // [n_cell][9][kRecFloats]
+  float* rec;               // split colour blocks: [9][n_cell][kRecFloats] (rec_index);
+                            // other models [n_cell][9][their record floats]
   double* part;             // cell partials: split colour blocks FP32, [kMaxWpc][n_cell]
                             // [kPartStride] (one set per cell wave); other models FP64,
                             // one set per cell (kPart3, kPartF, kPartG doubles)

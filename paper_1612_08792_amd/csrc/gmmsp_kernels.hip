@@ -140,7 +140,7 @@ __device__ __forceinline__ float eval_l_o(const AS4 float* f, float o1, float o2
 }
 
 template <int NP, bool kLdsOff = false>
-__device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (&xr)[NP],
+__device__ __forceinline__ void estep_pixels(const AS4 float* rec, size_t rs, const float (&xr)[NP],
                                              const float (&yr)[NP], const float (&L)[NP],
                                              const float (&A)[NP], const float (&B)[NP],
                                              float (&e)[NP][kSlots], float (&sum)[NP],
@@ -149,7 +149,7 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
   for (int p = 0; p < NP; ++p) sum[p] = 0.f;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
-    const AS4 float* f = rec + s * kRecFloats;
+    const AS4 float* f = rec + s * rs;
     float l[NP];
     if constexpr (kLdsOff) {
       float o[5];
@@ -182,7 +182,7 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
         float m = -INFINITY;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-          lv[s] = eval_l(rec + s * kRecFloats, xr[p], yr[p], L[p], A[p], B[p]);
+          lv[s] = eval_l(rec + s * rs, xr[p], yr[p], L[p], A[p], B[p]);
           m = fmaxf(m, lv[s]);
         }
         float t = 0.f;
@@ -201,7 +201,7 @@ __device__ __forceinline__ void estep_pixels(const AS4 float* rec, const float (
 // M-step sufficient statistics of NP pixels (weights inv[p] = 1 / sum[p], or 0
 // for a masked pixel) added to the 9 x 13 per-lane accumulators.
 template <int NP>
-__device__ __forceinline__ void accumulate_stats(const AS4 float* rec, float* acc,
+__device__ __forceinline__ void accumulate_stats(const AS4 float* rec, size_t rs, float* acc,
                                                  const float (&e)[NP][kSlots],
                                                  const float (&inv)[NP], const float (&xr)[NP],
                                                  const float (&yr)[NP], const float (&L)[NP],
@@ -215,7 +215,7 @@ __device__ __forceinline__ void accumulate_stats(const AS4 float* rec, float* ac
   }
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
-    const AS4 float* f = rec + s * kRecFloats;
+    const AS4 float* f = rec + s * rs;
     const float mL = f[R_ML], ma = f[R_MA], mb = f[R_MB];
     float* a = acc + s * kStats;
 #pragma unroll
@@ -277,8 +277,10 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
   const int npix = w * h;
   const int64_t pix0 = Ip->pix_off + (int64_t)y0 * W + x0;
   const float* img = lab + 3 * pix0;
-  const AS4 float* rec0 = cptr(P.rec) + (size_t)cell * (kSlots * kRecFloats);
+  // the cell's slot-0 record; slot s is s * rs floats further (rec_index)
+  const AS4 float* rec0 = cptr(P.rec) + rec_index(P.n_cell, cell, 0);
   const AS4 float* rec = rec0;
+  const size_t rs = (size_t)P.n_cell * kRecFloats;
 
   if (MODE == M_EXPORT_CAND) {
     const int nx = Ip->nx, ny = Ip->ny;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       for (int s = 0; s < kSlots; ++s) {
         const int kx = ccx + (s % 3) - 1, ky = ccy + (s / 3) - 1;
         const bool idx_ok = kx >= 0 && kx < nx && ky >= 0 && ky < ny;
-        const bool rec_ok = rec[s * kRecFloats + R_C] != -INFINITY;
+        const bool rec_ok = rec[s * rs + R_C] != -INFINITY;
         dst[s] = (idx_ok != rec_ok) ? -2 : (idx_ok ? ky * nx + kx : -1);
       }
     }
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     __shared__ float s_off[kWavesPerBlock * kOffBlock];
     float* woff = s_off + (threadIdx.x >> 6) * kOffBlock;
     constexpr int kOffIdx[5] = {R_O1, R_O2, R_O3, R_O4, R_OL};
-    stage_offsets(woff, P.rec + (size_t)cell * (kSlots * kRecFloats), kRecFloats, kOffIdx, lane);
+    stage_offsets(woff, P.rec + rec_index(P.n_cell, cell, 0), rs, kOffIdx, lane);
     for (int rd = sub; rd < n_pair; rd += wpc) {
       const int base = rd << 7;
       // The 144 record floats do not fit the scalar registers; an opaque zero
@@ -338,11 +340,11 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       // 45 vector registers
       int vz = 0;
       asm volatile("" : "+v"(vz));
-      estep_pixels<2, true>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
+      estep_pixels<2, true>(rec, rs, xr, yr, L, A, B, e, sum, shift, woff + vz);
       const float inv[2] = {__builtin_amdgcn_rcpf(sum[0]), v2 ? __builtin_amdgcn_rcpf(sum[1]) : 0.f};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
       llacc += v2 ? __builtin_amdgcn_logf(sum[1]) + shift[1] : 0.f;
-      accumulate_stats<2>(rec, acc, e, inv, xr, yr, L, A, B);
+      accumulate_stats<2>(rec, rs, acc, e, inv, xr, yr, L, A, B);
       advance(r1, c1, dr, dc, w);
       advance(r2, c2, dr, dc, w);
     }
@@ -352,10 +354,10 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const float xr[1] = {(float)c1}, yr[1] = {(float)r1};
       const float L[1] = {q1[0]}, A[1] = {q1[1]}, B[1] = {q1[2]};
       float e[1][kSlots], sum[1], shift[1];
-      estep_pixels<1, true>(rec, xr, yr, L, A, B, e, sum, shift, woff);
+      estep_pixels<1, true>(rec, rs, xr, yr, L, A, B, e, sum, shift, woff);
       const float inv[1] = {__builtin_amdgcn_rcpf(sum[0])};
       llacc += __builtin_amdgcn_logf(sum[0]) + shift[0];
-      accumulate_stats<1>(rec, acc, e, inv, xr, yr, L, A, B);
+      accumulate_stats<1>(rec, rs, acc, e, inv, xr, yr, L, A, B);
     }
     wave_reduce_scatter<kSlots * kStats>(acc, lane);
     const int r = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     __shared__ float s_off[kWavesPerBlock * kOffBlock];
     float* woff = s_off + (threadIdx.x >> 6) * kOffBlock;
     constexpr int kOffIdx[5] = {R_O1, R_O2, R_O3, R_O4, R_OL};
-    stage_offsets(woff, P.rec + (size_t)cell * (kSlots * kRecFloats), kRecFloats, kOffIdx, lane);
+    stage_offsets(woff, P.rec + rec_index(P.n_cell, cell, 0), rs, kOffIdx, lane);
     int r1 = lane / w, c1 = lane - r1 * w;
     int r2 = (lane + 64) / w, c2 = (lane + 64) - r2 * w;
     const int dr = 128 / w, dc = 128 - (128 / w) * w;
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       float e[2][kSlots], sum[2], shift[2];
       int vz = 0;
       asm volatile("" : "+v"(vz));
-      estep_pixels<2, true>(rec, xr, yr, L, A, B, e, sum, shift, woff + vz);
+      estep_pixels<2, true>(rec, rs, xr, yr, L, A, B, e, sum, shift, woff + vz);
       int best[2];
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const float xr[1] = {(float)col}, yr[1] = {(float)row};
       const float L[1] = {px[0]}, A[1] = {px[1]}, B[1] = {px[2]};
       float e[1][kSlots], sum[1], shift[1];
-      estep_pixels<1>(rec, xr, yr, L, A, B, e, sum, shift);
+      estep_pixels<1>(rec, rs, xr, yr, L, A, B, e, sum, shift);
       const float inv = __builtin_amdgcn_rcpf(sum[0]);
       float* dst = out_f + (size_t)(pix0 + (int64_t)row * W + col) * kSlots;
 #pragma unroll

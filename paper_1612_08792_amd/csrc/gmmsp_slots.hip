@@ -122,7 +122,7 @@ __device__ __forceinline__ void slot_cell(const DevPtrs& P, const float* __restr
   const int q = lane - kQ * s;
   const bool live = s < kSlots;
   const float4* rp = reinterpret_cast<const float4*>(
-      P.rec + ((size_t)cell * kSlots + (live ? s : kSlots - 1)) * kRecFloats);
+      P.rec + rec_index(P.n_cell, cell, live ? s : kSlots - 1));
   const float4 f0 = rp[0], f1 = rp[1], f2 = rp[2], f3 = rp[3];
   const float L11 = f0.x, L12 = f0.y, O1 = f0.z, O2 = f0.w;
   const float L22 = f1.x, SL = f1.y, O3 = f1.z, O4 = f1.w;

@@ -101,15 +101,15 @@ constexpr int kOffStride = 8;
 constexpr int kOffBlock = kSlots * kOffStride;  // floats per wave
 
 // lanes 0..kSlots-1 copy the offsets idx[0..N) of their slot's record (rec_cell:
-// the cell's nine records, rec_floats each); every lane of the wave may read the
+// the cell's slot-0 record, slot s at s * rec_stride floats); every lane of the wave may read the
 // block after the call.  Only the calling wave touches its block, so a wave
 // barrier orders the writes before the reads.
 template <int N>
-__device__ __forceinline__ void stage_offsets(float* woff, const float* rec_cell, int rec_floats,
+__device__ __forceinline__ void stage_offsets(float* woff, const float* rec_cell, size_t rec_stride,
                                               const int (&idx)[N], int lane) {
   static_assert(N <= 5, "at most five offsets per record");
   if (lane < kSlots) {
-    const float* g = rec_cell + lane * rec_floats;
+    const float* g = rec_cell + (size_t)lane * rec_stride;
 #pragma unroll
     for (int i = 0; i < N; ++i) woff[lane * kOffStride + i] = g[idx[i]];
   }
