@@ -121,7 +121,11 @@ int gmmsp_workspace_bytes(int32_t n_images, const gmmsp_params* params, size_t* 
 /* Create a handle over caller-owned device workspace (at least
  * gmmsp_workspace_bytes, 256-byte aligned).  Uploads the batch tables and clears
  * the parameter records on `stream`, then synchronises it.  The handle must be
- * initialised with gmmsp_init_seeds or gmmsp_set_params before it iterates. */
+ * initialised with gmmsp_init_seeds or gmmsp_set_params before it iterates.
+ * Errors: those of gmmsp_workspace_bytes; E_INVAL for a null or misaligned
+ * workspace or a null out; E_SIZE for a workspace smaller than
+ * gmmsp_workspace_bytes; E_NOMEM when host memory for the tables runs out;
+ * E_HIP when an upload fails. */
 int gmmsp_create(int32_t n_images, const gmmsp_params* params, void* workspace_dev,
                  size_t workspace_bytes, void* stream, gmmsp_handle** out);
 
