@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const AS4 float* rec = rec0 + zero;
     const float* woff = woff0 + vz;
     const int row = p / w, col = p - row * w;
-    const float* px = img + 3 * (row * W + col);
+    const float* px = img + 3 * ((int64_t)row * W + col);
     const float L = px[0], A = px[1], B = px[2];
     const float xr = (float)col, yr = (float)row;
     float e[kSlots];

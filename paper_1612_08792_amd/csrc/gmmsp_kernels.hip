@@ -331,8 +331,8 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       asm volatile("" : "+s"(zero));
       const AS4 float* rec = rec0 + zero;
       const bool v2 = base + 64 + lane < npix;
-      const float* q1 = img + 3 * (r1 * W + c1);
-      const float* q2 = img + (v2 ? 3 * (r2 * W + c2) : 3 * (r1 * W + c1));
+      const float* q1 = img + 3 * ((int64_t)r1 * W + c1);
+      const float* q2 = img + (v2 ? 3 * ((int64_t)r2 * W + c2) : 3 * ((int64_t)r1 * W + c1));
       const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
       const float xr[2] = {(float)c1, (float)c2}, yr[2] = {(float)r1, (float)r2};
       float e[2][kSlots], sum[2], shift[2];
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     }
     // the last round (at most 64 pixels) falls to the wave whose turn it is
     if (n_pair % wpc == sub && (n_pair << 7) + lane < npix) {
-      const float* q1 = img + 3 * (r1 * W + c1);
+      const float* q1 = img + 3 * ((int64_t)r1 * W + c1);
       const float xr[1] = {(float)c1}, yr[1] = {(float)r1};
       const float L[1] = {q1[0]}, A[1] = {q1[1]}, B[1] = {q1[2]};
       float e[1][kSlots], sum[1], shift[1];
@@ -384,8 +384,8 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
       const bool v1 = base + lane < npix, v2 = base + 64 + lane < npix;
       const int y1 = v1 ? r1 : 0, x1 = v1 ? c1 : 0;
       const int y2 = v2 ? r2 : y1, x2 = v2 ? c2 : x1;
-      const float* q1 = img + 3 * (y1 * W + x1);
-      const float* q2 = img + 3 * (y2 * W + x2);
+      const float* q1 = img + 3 * ((int64_t)y1 * W + x1);
+      const float* q2 = img + 3 * ((int64_t)y2 * W + x2);
       const float L[2] = {q1[0], q2[0]}, A[2] = {q1[1], q2[1]}, B[2] = {q1[2], q2[2]};
       const float xr[2] = {(float)x1, (float)x2}, yr[2] = {(float)y1, (float)y2};
       float e[2][kSlots], sum[2], shift[2];
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) CELLS_ATTR void k_cells(DevPtrs P, const float
     int row = lane / w, col = lane - (lane / w) * w;
     const int drow = 64 / w, dcol = 64 - (64 / w) * w;
     for (int p = lane; p < npix; p += 64) {
-      const float* px = img + 3 * (row * W + col);
+      const float* px = img + 3 * ((int64_t)row * W + col);
       const float xr[1] = {(float)col}, yr[1] = {(float)row};
       const float L[1] = {px[0]}, A[1] = {px[1]}, B[1] = {px[2]};
       float e[1][kSlots], sum[1], shift[1];
