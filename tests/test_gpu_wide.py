@@ -1,12 +1,14 @@
 """The widest image a batch may hold (2^24 pixels, GMMSP_MAX_WIDTH): two EM
-passes of the slot-lane pass on a 2^24 x 64 image made by repeating one
-1024 x 64 tile, a 1.07 Gpx image.  With a seed spacing of 32 the seed grid
-repeats with the tile, and two passes reach only a few cells, so the
-superpixels of the image's first tile have the parameters of the first tile of
-a three-tile image, and those of its last-but-one tile (the pixels at the
-largest offsets the pass addresses) the parameters of the three-tile image's
-middle tile, moved by the tiles between them.  The three-tile image goes
-through the FP64 oracle; the bar is the trajectory tolerance."""
+passes on a 2^24-pixel-wide image made by repeating one 1024-pixel-wide tile
+(64 rows with the slot-lane pass, 1.07 Gpx; 96 rows with cells 48 rows tall
+and the pixel-lane pass, 1.61 Gpx, where a cell's last rows sit more than 2^31
+floats past its first pixel).  The seed grid repeats with the tile and two
+passes reach only a few cells, so the superpixels of the image's first tile
+have the parameters of the first tile of a three-tile image, and those of its
+last-but-one tile (the largest offsets) the parameters of the three-tile
+image's middle tile, moved by the tiles between them.  The three-tile image
+goes through the FP64 oracle; the bar is the trajectory tolerance.  The labels
+of the last-but-one tile repeat those of the second tile."""
 import sys
 
 import numpy as np
@@ -20,8 +22,8 @@ from parity_helpers import assert_theta_close
 
 pytestmark = pytest.mark.gpu
 
-TW, H, V = 1024, 64, 32   # tile width, image height, seed spacing
-W = 1 << 24               # the widest image
+TW, VX = 1024, 32   # tile width, seed spacing along x
+W = 1 << 24         # the widest image
 
 
 def say(*a):
@@ -29,29 +31,38 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_widest_image_matches_oracle_at_both_ends():
+@pytest.mark.parametrize("kind,vy", [(1, 32), (0, 48)])
+def test_widest_image_matches_oracle_at_both_ends(kind, vy):
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     dev = torch.device("cuda:0")
-    tile = synth.voronoi_lab(TW, H, 40, 3.0, 21, (TW // V) * (H // V)).lab  # (H, TW, 3)
-    g3 = O.make_grid(3 * TW, H, vx=V, vy=V)
+    H = 2 * vy
+    tile = synth.voronoi_lab(TW, H, 40, 3.0, 21, (TW // VX) * 2).lab  # (H, TW, 3)
+    g3 = O.make_grid(3 * TW, H, vx=VX, vy=vy)
     want = O.theta_to_rows(O.run_em(tile.repeat(1, 3, 1).numpy(), g3, max_iters=2)["theta"])
 
-    say(f"{W}x{H} image ({W * H / 1e9:.2f} Gpx), seed spacing {V}, T 2")
+    say(f"{W}x{H} image ({W * H / 1e9:.2f} Gpx), seed spacing {VX}x{vy}, "
+        f"statistics pass kind {kind}, T 2")
     lab = tile.to(dev).repeat(1, W // TW, 1).reshape(-1).contiguous()
-    m = GMMSP([(W, H)], v=V, device=dev)
-    m.set_estep_kernel(1)
+    m = GMMSP([(W, H)], v=(VX, vy), device=dev)
+    m.set_estep_kernel(kind)
     m.init_seeds(lab)
     assert list(m.em_iterate(lab, 2)) == [2]
     rows = m.get_params()
+    labels, _ = m.label(lab, want_ll=False)
+    labels = labels.view(H, W)
+    second = labels[:, TW:2 * TW].cpu().numpy()
+    far = labels[:, W - 2 * TW:W - TW].cpu().numpy()
     m.close()
-    del lab, m
+    del lab, labels, m
     torch.cuda.empty_cache()
 
-    nx, n3, per = W // V, 3 * TW // V, TW // V
-    ky = np.repeat(np.arange(H // V), per)
-    kx = np.tile(np.arange(per), H // V)
+    nx, n3, per = W // VX, 3 * TW // VX, TW // VX
+    ky = np.repeat(np.arange(2), per)
+    kx = np.tile(np.arange(per), 2)
     e0 = assert_theta_close(rows[ky * nx + kx], want[ky * n3 + kx], 1e-3, what="first tile")
-    far = rows[ky * nx + (nx - 2 * per) + kx].copy()
-    far[:, 0] -= W - 3 * TW          # x of the last-but-one tile against the middle tile
-    e1 = assert_theta_close(far, want[ky * n3 + per + kx], 1e-3, what="last-but-one tile")
-    say("first tile", e0, "last-but-one tile", e1)
+    got = rows[ky * nx + (nx - 2 * per) + kx].copy()
+    got[:, 0] -= W - 3 * TW          # x of the last-but-one tile against the middle tile
+    e1 = assert_theta_close(got, want[ky * n3 + per + kx], 1e-3, what="last-but-one tile")
+    agree = float((far - (W // TW - 3) * per == second).mean())
+    say("first tile", e0, "last-but-one tile", e1, "labels repeated", agree)
+    assert agree >= 0.999
