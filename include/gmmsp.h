@@ -184,7 +184,7 @@ int gmmsp_ll_history(gmmsp_handle* h, int32_t b, double* out_host, int32_t cap,
 
 /* Final E-step with the current theta and the labelling of Eq. obtLi: labels_dev
  * (int32, one per pixel, packed like the image) receives argmax_k R_ik, ties to
- * the smallest k.  ll_host (nullable, n_images doubles) receives L(theta) of this
+ * the smallest k; k is the superpixel's index within its own image, k_y n_x + k_x.  ll_host (nullable, n_images doubles) receives L(theta) of this
  * E-step.  Synchronises `stream` only when ll_host is given. */
 int gmmsp_label(gmmsp_handle* h, const float* lab_dev, int32_t* labels_dev,
                 double* ll_host, void* stream);

@@ -1321,7 +1321,8 @@ static ConnSizes conn_sizes(const gmmsp_handle* h) {
   ConnSizes z;
   z.max_pix = z.max_tiles = z.max_w = z.max_h = 0;
   for (const ImgDesc& I : h->img) {
-    z.max_pix = std::max(z.max_pix, I.W * I.H);
+    // (clamped: the connectivity step itself rejects batches of 2^31 - 1 pixels or more)
+    z.max_pix = (int)std::max<int64_t>(z.max_pix, std::min<int64_t>((int64_t)I.W * I.H, INT32_MAX));
     z.max_w = std::max(z.max_w, I.W);
     z.max_h = std::max(z.max_h, I.H);
     z.max_tiles = std::max(z.max_tiles, (int)gmmsp::conn_tiles(I.W, I.H));

@@ -66,3 +66,32 @@ def test_widest_image_matches_oracle_at_both_ends(kind, vy):
     agree = float((far - (W // TW - 3) * per == second).mean())
     say("first tile", e0, "last-but-one tile", e1, "labels repeated", agree)
     assert agree >= 0.999
+
+
+def test_batch_beyond_2_31_pixels():
+    """260 copies of one 3840x2160 image in one batch (2.16 Gpx, more than
+    2^31 pixels): the last image, whose pixels start past 2^31, gets the same
+    bits as the first (theta, L history, labels)."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    im = synth.config5_batch(device=dev, n_images=1)[0]
+    n = (1 << 31) // (im.W * im.H) + 2
+    say(f"{n} x {im.W}x{im.H} ({n * im.W * im.H / 1e9:.2f} Gpx), K {im.K}, T 2")
+    lab = im.lab.reshape(-1).repeat(n).contiguous()
+    m = GMMSP([(im.W, im.H)] * n, K=im.K, device=dev)
+    m.set_estep_kernel(1)
+    m.init_seeds(lab)
+    assert set(m.em_iterate(lab, 2)) == {2}
+    rows = m.get_params()
+    labels, _ = m.label(lab, want_ll=False)
+    first, last = m.image_slice(0), m.image_slice(n - 1)
+    l0 = labels[first].cpu().numpy()
+    l1 = labels[last].cpu().numpy()   # labels are superpixel indices within the image
+    h0, h1 = m.ll_history(0), m.ll_history(n - 1)
+    s0, s1 = rows[m.sp_slice(0)], rows[m.sp_slice(n - 1)]
+    m.close()
+    del lab, labels, m
+    torch.cuda.empty_cache()
+    assert np.array_equal(s0, s1)
+    assert np.array_equal(h0, h1)
+    assert np.array_equal(l0, l1)
